@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of batched dynamic relaxation on one MI355X.
+
+Workload (default): 256 random kNN fiber networks, node counts uniform in
+1000..5000, FP64, F = I + sym U(+-0.01), relative residual 1e-8, damping
+2.5e-4, solved by one persistent launch per step through the C ABI.  A step
+is one solve of every network to convergence (set-up, DR loop, stress) with
+the stress read back to the host.
+
+Metric: fiber-element updates/s = sum_p fibers_p * passes_p / wall time.
+Beside it: the same networks' per-problem launch loop (a sample solved to
+convergence) and the CPU oracle (a bounded sample, all host threads).
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work of one fiber-element update (one DR pass over one fiber,
+# with its share of the per-node work), counted once per fiber:
+#   fiber: d (3), l^2 (5), k (l^2 - L^2) / l (4), force on both ends (9)  = 21
+#   node (x0.47 nodes per fiber): update x (6), damped acceleration (6),
+#   two half velocity updates (12), |g|^2 (6), m |v|^2 (7)                 = 37 -> 17
+FLOP_PER_UPDATE = 38.0
+# Compulsory HBM bytes per fiber-update if the nodal state lived in HBM
+# (FP64: per free node u, v read+write 96 B; per node X 24 B, 1/m 8 B, row
+# pointer 4 B; per fiber 2 incidences x (4 B index + 16 B constants)).
+BYTES_PER_UPDATE = 104.0
+PEAK_FP64_VECTOR = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch, beta, tol, target_s=15.0):
+    """The oracle, untuned, on a bounded sample: the first C networks, a fixed
+    number of DR passes each, one network per thread (C = host threads, at
+    most 16)."""
+    import numpy as np
+
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    O.build(force=False)
+    C = max(1, min(16, os.cpu_count() or 1))
+    sub = batch.subset(range(min(C, len(batch))))
+    # calibrate the pass count on one network
+    t = time.perf_counter()
+    O.solve(sub.nets[0], sub.F[0], tol=1e-300, max_iter=500, beta=beta, dt_safety=0.9)
+    per_pass = (time.perf_counter() - t) / 500 / sub.nets[0].n_fibers
+    mean_m = np.mean([n.n_fibers for n in sub.nets])
+    passes = int(max(1000, min(200000, target_s / (per_pass * mean_m))))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=C) as ex:
+        res = list(ex.map(lambda i: O.solve(sub.nets[i], sub.F[i], tol=1e-300, max_iter=passes,
+                                            beta=beta, dt_safety=0.9), range(len(sub))))
+    wall = time.perf_counter() - t
+    upd = sum(n.n_fibers * r.iters for n, r in zip(sub.nets, res))
+    return {"value": upd / wall, "unit": "fiber-updates/s", "cores": C, "kind": "oracle",
+            "sample": f"first {len(sub)} networks of the batch, {passes} DR passes each "
+                      f"(fixed pass count), one network per thread, {wall:.1f}s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "single"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--placement", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-loop", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sub-problems are independent; see the design notes on sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dr.load()
+    if args.workload == "uniform":
+        batch, beta, tol = I.config_uniform_batch(256), 2.5e-4, 1e-8
+        wl = "256 kNN(k=3) fiber networks, N ~ U{1000..5000}, F = I + sym U(+-0.01), FP64, tol 1e-8"
+    else:
+        batch, beta, tol = I.config_single(), 1e-3, 1e-8
+        wl = "1 kNN(k=3) fiber network, N = 500, F = diag(1.01,1,1), FP64, tol 1e-8"
+    log("workload:", wl, "networks", len(batch), "fibers", batch.total_fibers)
+    stream = torch.cuda.current_stream()
+    b = dr.DRBatch(batch, tol=tol, damping=beta, dt_safety=0.9, block=args.block,
+                   placement=args.placement, stream=stream.cuda_stream)
+    info = b.info()
+    log("launch:", info)
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    M = np.array([n.n_fibers for n in batch.nets], np.float64)
+
+    for w in range(args.warmup):
+        b.solve_device(Fd)
+        r = b.results()
+        log(f"warmup {w}: passes min/median/max {r['iters'].min()}/{int(np.median(r['iters']))}/{r['iters'].max()}")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    updates = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        b.solve_device(Fd)
+        ev[k][1].record(stream)
+        r = b.results()  # waits; sigma, status and pass counts to the host
+        updates += float((M * r["iters"]).sum())
+        log(f"step {k}: {ev[k][0].elapsed_time(ev[k][1]):.1f} ms kernels")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_s = sum(a.elapsed_time(e) for a, e in ev) / 1e3 / args.steps
+    assert (r["result"] == dr.DR_CONVERGED).all(), "not every network converged"
+    value = updates / wall
+    per_launch = updates / args.steps
+    flops = FLOP_PER_UPDATE * per_launch / kern_s
+    hbm_equiv = BYTES_PER_UPDATE * per_launch / kern_s
+    out = {
+        "metric": "fiber-element updates/s (batched persistent launch)",
+        "value": value,
+        "unit": "fiber-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "networks": len(batch), "fibers": int(M.sum()),
+                   "damping": beta, "dt_safety": 0.9, "block": info["block"],
+                   "nodes_per_thread": info["nodes_per_thread"], "lds_bytes": info["lds_bytes"],
+                   "passes_min": int(r["iters"].min()), "passes_max": int(r["iters"].max()),
+                   "passes_median": int(np.median(r["iters"]))},
+        "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / PEAK_FP64_VECTOR, "traffic": None,
+                     "kernel": "k_dr_reg" if info["nodes_per_thread"] > 0 else "k_dr_glb",
+                     "kernel_ms": kern_s * 1e3,
+                     "flop_per_update": FLOP_PER_UPDATE,
+                     "hbm_equivalent_GBps": hbm_equiv / 1e9,
+                     "hbm_equivalent_frac": hbm_equiv / PEAK_HBM},
+    }
+    if not args.no_loop:
+        sizes = np.array([n.n_nodes for n in batch.nets])
+        i = int(np.argmin(sizes))
+        lb = dr.DRBatch(batch.subset([i]), tol=tol, damping=beta, dt_safety=0.9,
+                        stream=stream.cuda_stream)
+        t = time.perf_counter()
+        lb.solve_loop()
+        lw = time.perf_counter() - t
+        lr = lb.results()
+        lupd = float(M[i] * lr["iters"][0])
+        out["loop_baseline"] = {"value": lupd / lw, "unit": "fiber-updates/s",
+                                "sample": f"network {i} (N={sizes[i]}, {int(M[i])} fibers) solved "
+                                          f"to convergence by the per-problem launch loop: "
+                                          f"{int(lr['iters'][0])} passes in {lw:.2f}s",
+                                "passes": int(lr["iters"][0]),
+                                "batched_passes": int(r["iters"][i]),
+                                "speedup_batched_over_loop": value / (lupd / lw)}
+        lb.close()
+        log("loop baseline:", out["loop_baseline"])
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(batch, beta, tol)
+        log("cpu baseline:", out["cpu_baseline"])
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

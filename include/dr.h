@@ -1,0 +1,226 @@
+/*
+ * dr.h -- C ABI of libdr: batched dynamic relaxation (DR) of many small,
+ * independent pin-jointed fiber networks on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Merson & Shephard, "Using Hierarchical Parallelism to Accelerate
+ * the Solution of Many Small Partial Differential Equations".  Section II
+ * states the sub-problem (a fiber network at a macroscale material point,
+ * relaxed to static equilibrium by damped explicit pseudo-dynamics whose
+ * force residual is monitored); section III, Fig. 1, gives the loop; section
+ * I says each sub-problem hands constitutive information (here the volume
+ * averaged Cauchy stress) back to the macroscale.
+ *
+ * Readings where the paper is silent, applied by every entry point below:
+ *   fiber law    T = EA (lambda^2 - 1) / 2 along the current fiber direction;
+ *   lumped mass  m_i = 1/2 sum of the lengths of the fibers at node i;
+ *   time step    dt = dt_safety * 2 / w, w^2 = max over free nodes of
+ *                (2 / m_i) sum_{f at i} 1.1 EA_f / L_f, constant per solve;
+ *   damping      f_d = -c m v with c = damping * w;
+ *   start        prescribed nodes u = (F - I) X; free nodes from the affine
+ *                field (F - I) X, from zero, or warm (u_prev + (F - F_prev) X);
+ *   residual     rho = |g_free| / max(|g_prescribed|, 1e-4 mean(EA)
+ *                sqrt(3 max(N_B, 1))), tested after every pass of the
+ *                repeat-until loop (so at least one pass is made);
+ *   stress       sigma = 1/det(F) sum_{b prescribed} (-g_b) (x) (x_b - F c0),
+ *                c0 = (1/2, 1/2, 1/2), reference volume 1 (the unit cube),
+ *                row-major sigma[3 p + q] = sum r_p y_q; the fiber (virial)
+ *                form sum_f T_f d_f (x) d_f / l_f / det(F) is returned too.
+ *
+ * Conventions shared by all entry points
+ *   - Every call returns a dr_status; on error a message is available from
+ *     dr_last_error() (thread-local, valid until the next libdr call on the
+ *     same thread).  No C++ exception crosses this interface.
+ *   - Pointers are host pointers unless the name says "_device".
+ *   - Inputs are copied before the call returns; the caller keeps ownership
+ *     of every array it passes and libdr never frees caller memory.
+ *   - A dr_batch owns all device memory it allocates; dr_batch_destroy
+ *     releases it.  A handle is used by one host thread at a time; all of its
+ *     device work is ordered on the HIP stream given at creation.
+ *   - F is a 3x3 deformation gradient, row-major, F[3 i + j] = dx_i / dX_j.
+ *   - Node ids are the caller's (problem-local, 0-based) ids; u is always
+ *     returned in the caller's node order.
+ *   - Non-convergence is not a call error: it is reported per problem in
+ *     `result` (dr_result).
+ */
+#ifndef DR_H
+#define DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dr_batch dr_batch; /* opaque handle, owned by libdr */
+
+typedef enum {
+    DR_OK = 0,
+    DR_E_INVALID = -1, /* bad argument or network; message names it */
+    DR_E_NOMEM = -2,   /* host or device allocation failed */
+    DR_E_DEVICE = -3,  /* HIP runtime error (no device, launch failure, ...) */
+    DR_E_STATE = -4    /* call out of order (e.g. dr_stress before dr_solve) */
+} dr_status;
+
+typedef enum {
+    DR_CONVERGED = 0, /* rho <= tol */
+    DR_MAX_ITER = 1,  /* max_iter passes made without reaching tol */
+    DR_NONFINITE = 2  /* a residual or energy became NaN / Inf */
+} dr_result;
+
+typedef enum { DR_FP64 = 0, DR_FP32 = 1 } dr_precision;
+
+typedef enum {
+    DR_PLACE_AUTO = 0,   /* LDS when the largest problem fits, else global */
+    DR_PLACE_LDS = 1,    /* positions in LDS, node state in registers */
+    DR_PLACE_GLOBAL = 2  /* positions and velocities in device memory */
+} dr_placement;
+
+typedef enum {
+    DR_START_AFFINE = 0, /* free nodes start at (F - I) X (cold start) */
+    DR_START_ZERO = 1,   /* free nodes start at u = 0 (Fig. 1, commented init) */
+    DR_START_WARM = 2    /* u_prev + (F - F_prev) X from the problem's last solve */
+} dr_start;
+
+/*
+ * A packed batch of networks (the paper's PackedView idea, section III:
+ * one row-offset array plus one value array holding every sub-problem).
+ *   n_problems          >= 1
+ *   node_offsets        [n_problems + 1], non-decreasing, node_offsets[0] = 0
+ *   fiber_offsets       [n_problems + 1], non-decreasing, fiber_offsets[0] = 0
+ *   X                   [total_nodes * 3] reference coordinates, xyz
+ *                       interleaved, finite; the network lives in the unit cube
+ *   fiber_nodes         [total_fibers * 2] problem-local node ids (a, b), a != b
+ *   EA                  [total_fibers] finite and > 0
+ *   fixed               [total_nodes] 1 = prescribed node, 0 = free
+ * Each problem needs >= 1 node, every free node needs >= 1 fiber and every
+ * fiber a nonzero reference length.
+ */
+typedef struct {
+    int32_t n_problems;
+    const int64_t *node_offsets;
+    const int64_t *fiber_offsets;
+    const double *X;
+    const int32_t *fiber_nodes;
+    const double *EA;
+    const uint8_t *fixed;
+} dr_networks;
+
+/*
+ * Solver options (see the readings above).
+ *   precision   DR_FP64 (FP64 state) or DR_FP32 (FP32 nodal state and force
+ *               gather, FP64 norm reductions and stress)
+ *   tol         > 0, convergence threshold on rho
+ *   max_iter    >= 1, cap on DR passes per solve
+ *   damping     >= 0, c = damping * w (dimensionless)
+ *   dt_safety   in (0, 1], dt = dt_safety * 2 / w
+ *   block       threads per workgroup: 0 = automatic, else 256, 512 or 1024
+ *   placement   a dr_placement value; DR_PLACE_LDS is rejected at creation
+ *               when the largest problem does not fit (3 * 8 B per node of
+ *               LDS, at most 8 nodes per thread)
+ */
+typedef struct {
+    int32_t precision;
+    double tol;
+    int64_t max_iter;
+    double damping;
+    double dt_safety;
+    int32_t block;
+    int32_t placement;
+} dr_options;
+
+/* Fills *opt with the defaults: FP64, tol 1e-8, max_iter 2000000,
+ * damping 1e-3, dt_safety 0.9, block 0, placement DR_PLACE_AUTO. */
+void dr_options_default(dr_options *opt);
+
+/*
+ * Validates and packs the networks (Fig. 1 steps 1-3: edge connectivity,
+ * connectivity array, transfer to the device; step 5: lumped mass), computes
+ * dt, c and the residual floor per problem, and uploads everything to HBM.
+ *   nets, opt     read only; copied
+ *   hip_stream    a hipStream_t (NULL = the default stream); all later device
+ *                 work of the batch is enqueued on it
+ *   out           receives the new handle (NULL on failure)
+ * Errors: DR_E_INVALID (the message names problem and element), DR_E_NOMEM,
+ * DR_E_DEVICE.  Validation runs before any HIP call.
+ */
+dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt,
+                          void *hip_stream, dr_batch **out);
+
+/*
+ * Enqueues one DR solve (Fig. 1 steps 4, 6, 7 and the loop, then the stress
+ * average) for the problems listed in ids, asynchronously on the stream.
+ *   F       [n_ids * 9] host, F of ids[k] at F + 9 k; copied before return
+ *   ids     [n_ids] distinct problem indices in [0, n_problems), or NULL for
+ *           all problems in order (n_ids must then equal n_problems)
+ *   start   a dr_start value; DR_START_WARM uses the state the problem's
+ *           previous solve left on the device (affine if it has none)
+ * Errors: DR_E_INVALID (bad ids / F not finite / det F <= 0), DR_E_DEVICE.
+ */
+dr_status dr_solve(dr_batch *b, const double *F, const int32_t *ids,
+                   int32_t n_ids, int32_t start);
+
+/*
+ * As dr_solve, with F_device [n_ids * 9] and ids_device [n_ids] already in
+ * device memory (ids_device may be NULL for all problems in order).  The
+ * arrays must stay valid until the solve has finished on the stream.  No
+ * host-device copy is enqueued; the ids are not validated on the host.
+ */
+dr_status dr_solve_device(dr_batch *b, const double *F_device,
+                          const int32_t *ids_device, int32_t n_ids, int32_t start);
+
+/*
+ * Waits for the last solve and returns its results, in the order of that
+ * solve's ids.  Any output pointer may be NULL.
+ *   sigma      [n_ids * 9]  boundary (reaction) form of the Cauchy stress
+ *   sigma_fib  [n_ids * 9]  fiber (virial) form
+ *   u          [total_nodes * 3] displacements of ALL problems of the batch,
+ *              caller node order, xyz interleaved (the problems not in the
+ *              last solve keep their previous state)
+ *   result     [n_ids] dr_result
+ *   iters      [n_ids] DR passes made
+ *   resid      [n_ids] final rho
+ *   ke         [n_ids] final kinetic energy 1/2 sum m |v|^2
+ * Errors: DR_E_STATE (no solve yet), DR_E_DEVICE.
+ */
+dr_status dr_stress(dr_batch *b, double *sigma, double *sigma_fib, double *u,
+                    int32_t *result, int64_t *iters, double *resid, double *ke);
+
+/* Blocks until all work enqueued on the batch's stream has finished. */
+dr_status dr_sync(dr_batch *b);
+
+/*
+ * Per-problem launch loop (the paper's "naive" design, section III): the same
+ * iteration as dr_solve, run for one problem at a time with a few kernel
+ * launches per DR pass and the residual read back and tested on the host
+ * after every pass.  Comparator only; same arguments and results as
+ * dr_solve followed by dr_stress for the given ids, and synchronous.
+ */
+dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids,
+                        int32_t n_ids, int32_t start);
+
+/* Information about the packed batch and the launch chosen for it.
+ *   n_problems, total_nodes, total_fibers, block (threads per workgroup),
+ *   lds_bytes (dynamic LDS per workgroup), nodes_per_thread. Any may be NULL. */
+dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_nodes,
+                        int64_t *total_fibers, int32_t *block, int32_t *lds_bytes,
+                        int32_t *nodes_per_thread);
+
+/*
+ * Per-problem derived scalars computed at creation: dt, c and the residual
+ * floor, each [n_problems] (any may be NULL).  Host only.
+ */
+dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor);
+
+/* Releases the handle and its device memory (waits for its stream first).
+ * NULL is ignored. */
+void dr_batch_destroy(dr_batch *b);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DR_H */

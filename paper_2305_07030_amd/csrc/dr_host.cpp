@@ -1,0 +1,771 @@
+// libdr host side: argument validation, packing of a batch of networks into
+// the device layout of dr_layout.h, per-problem constants, launch planning,
+// result retrieval, and the per-problem launch-loop comparator.
+//
+// Section III of the paper: the networks are packed once (edge connectivity,
+// connectivity array, one transfer to the device; prescribed degrees of
+// freedom reordered to a trailing block) and every later solve of the batch
+// is one kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dr.h"
+#include "dr_layout.h"
+
+using drk::KL;
+using drk::LaunchPlan;
+using drk::ProbDesc;
+using drk::SolveArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+dr_status fail(dr_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHECK(expr)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(DR_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                        __LINE__);                                                                \
+    } while (0)
+
+constexpr int kLdsLimit = 160 * 1024;
+constexpr int kMaxNpt = 8;
+
+// Host copy of one packed problem's node permutation (caller id -> local id).
+struct HostProblem {
+    int32_t N, N_free, M;
+    int64_t in_node_base; // caller's node offset
+    std::vector<int32_t> new_of_old;
+};
+
+template <class T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+} // namespace
+
+struct dr_batch {
+    dr_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int32_t P = 0;
+    int64_t total_nodes = 0, total_fibers = 0, total_slices = 0, total_inc = 0;
+    int32_t n_max = 0;
+    std::vector<HostProblem> hp;
+    std::vector<ProbDesc> desc;
+    // device arrays
+    ProbDesc *d_probs = nullptr;
+    double *d_X = nullptr, *d_invm = nullptr, *d_mass = nullptr;
+    int32_t *d_deg = nullptr, *d_slice_w = nullptr, *d_nbr = nullptr;
+    int64_t *d_slice_off = nullptr;
+    KL *d_kl = nullptr;
+    double *d_u = nullptr, *d_F_last = nullptr;
+    int32_t *d_has_state = nullptr;
+    double *d_xg = nullptr, *d_wg = nullptr;
+    // per-solve
+    double *d_F = nullptr;
+    int32_t *d_ids = nullptr, *d_order = nullptr;
+    double *d_sigma = nullptr, *d_sigma_fib = nullptr, *d_rho = nullptr, *d_ke = nullptr;
+    int64_t *d_iters = nullptr;
+    int32_t *d_status = nullptr;
+    double *d_partial = nullptr, *d_scalars = nullptr;
+    // pinned staging
+    double *h_F = nullptr;
+    int32_t *h_ids = nullptr, *h_order = nullptr;
+    double *h_scalars = nullptr;
+    hipEvent_t staged = nullptr;
+    // last solve
+    int32_t last_n = -1;
+    std::vector<int32_t> last_ids;
+    // One launch shape for every solve of the batch (fixed at creation from
+    // the largest problem), so a problem's arithmetic -- and its result, bit
+    // for bit -- does not depend on which other problems share the launch.
+    LaunchPlan plan{0, 0, 0};
+};
+
+namespace {
+
+void free_all(dr_batch *b)
+{
+    void *dev[] = {b->d_probs, b->d_X, b->d_invm, b->d_mass, b->d_deg, b->d_slice_w, b->d_nbr,
+                   b->d_slice_off, b->d_kl, b->d_u, b->d_F_last, b->d_has_state, b->d_xg,
+                   b->d_wg, b->d_F, b->d_ids, b->d_order, b->d_sigma, b->d_sigma_fib, b->d_rho,
+                   b->d_ke, b->d_iters, b->d_status, b->d_partial, b->d_scalars};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_scalars};
+    for (void *p : host)
+        if (p) (void)hipHostFree(p);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+}
+
+// 30-bit Morton key of a point in the unit cube (clamped).
+uint32_t morton3(const double *x)
+{
+    uint32_t key = 0;
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        double t = x[a];
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        q[a] = (uint32_t)(t * 1023.0);
+    }
+    for (int bit = 9; bit >= 0; --bit)
+        for (int a = 0; a < 3; ++a) key = (key << 1) | ((q[a] >> bit) & 1u);
+    return key;
+}
+
+dr_status validate_options(const dr_options *o)
+{
+    if (!o) return fail(DR_E_INVALID, "options is NULL");
+    if (o->precision != DR_FP64 && o->precision != DR_FP32)
+        return fail(DR_E_INVALID, "precision %d is not DR_FP64 or DR_FP32", o->precision);
+    if (o->precision == DR_FP32)
+        return fail(DR_E_INVALID, "precision DR_FP32 is not available in this build");
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol))
+        return fail(DR_E_INVALID, "tol must be finite and > 0 (got %g)", o->tol);
+    if (o->max_iter < 1) return fail(DR_E_INVALID, "max_iter must be >= 1");
+    if (!(o->damping >= 0.0) || !std::isfinite(o->damping))
+        return fail(DR_E_INVALID, "damping must be finite and >= 0 (got %g)", o->damping);
+    if (!(o->dt_safety > 0.0 && o->dt_safety <= 1.0))
+        return fail(DR_E_INVALID, "dt_safety must be in (0, 1] (got %g)", o->dt_safety);
+    if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024)
+        return fail(DR_E_INVALID, "block must be 0, 256, 512 or 1024 (got %d)", o->block);
+    if (o->placement < DR_PLACE_AUTO || o->placement > DR_PLACE_GLOBAL)
+        return fail(DR_E_INVALID, "placement %d is not a dr_placement value", o->placement);
+    return DR_OK;
+}
+
+// Host-side packing of all problems (no HIP calls).
+struct Packed {
+    std::vector<ProbDesc> desc;
+    std::vector<HostProblem> hp;
+    std::vector<double> X, invm, mass;
+    std::vector<int32_t> deg, slice_w, nbr;
+    std::vector<int64_t> slice_off;
+    std::vector<KL> kl;
+    int32_t n_max = 0;
+};
+
+dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
+{
+    if (!nets) return fail(DR_E_INVALID, "networks is NULL");
+    const int32_t P = nets->n_problems;
+    if (P < 1) return fail(DR_E_INVALID, "n_problems must be >= 1 (got %d)", P);
+    if (!nets->node_offsets || !nets->fiber_offsets || !nets->X || !nets->EA || !nets->fixed)
+        return fail(DR_E_INVALID, "a required network array is NULL");
+    const int64_t *no = nets->node_offsets, *fo = nets->fiber_offsets;
+    if (no[0] != 0 || fo[0] != 0) return fail(DR_E_INVALID, "offsets must start at 0");
+    for (int32_t p = 0; p < P; ++p) {
+        if (no[p + 1] - no[p] < 1)
+            return fail(DR_E_INVALID, "problem %d has no nodes", p);
+        if (no[p + 1] - no[p] > (int64_t)INT32_MAX / 4)
+            return fail(DR_E_INVALID, "problem %d has too many nodes", p);
+        if (fo[p + 1] < fo[p]) return fail(DR_E_INVALID, "fiber_offsets decrease at problem %d", p);
+    }
+    if (fo[P] > 0 && !nets->fiber_nodes) return fail(DR_E_INVALID, "fiber_nodes is NULL");
+
+    pk.desc.resize(P);
+    pk.hp.resize(P);
+    const int64_t total_nodes = no[P];
+    for (int64_t i = 0; i < 3 * total_nodes; ++i)
+        if (!std::isfinite(nets->X[i]))
+            return fail(DR_E_INVALID, "X[%lld] is not finite", (long long)i);
+
+    int64_t slice_base = 0, inc_base = 0, node_base = 0;
+    pk.X.resize(3 * total_nodes);
+    pk.invm.resize(total_nodes);
+    pk.mass.resize(total_nodes);
+    pk.deg.resize(total_nodes);
+
+    for (int32_t p = 0; p < P; ++p) {
+        const int32_t N = (int32_t)(no[p + 1] - no[p]);
+        const int64_t M64 = fo[p + 1] - fo[p];
+        if (M64 > INT32_MAX / 2) return fail(DR_E_INVALID, "problem %d has too many fibers", p);
+        const int32_t M = (int32_t)M64;
+        const double *X = nets->X + 3 * no[p];
+        const int32_t *fib = nets->fiber_nodes + 2 * fo[p];
+        const double *EA = nets->EA + fo[p];
+        const uint8_t *fixed = nets->fixed + no[p];
+
+        std::vector<double> L(M), L2(M);
+        std::vector<int32_t> degree(N, 0);
+        for (int32_t f = 0; f < M; ++f) {
+            const int32_t a = fib[2 * f], b = fib[2 * f + 1];
+            if (a < 0 || a >= N || b < 0 || b >= N)
+                return fail(DR_E_INVALID, "problem %d fiber %d: node id out of range (%d, %d; N=%d)",
+                            p, f, a, b, N);
+            if (a == b) return fail(DR_E_INVALID, "problem %d fiber %d joins node %d to itself", p, f, a);
+            if (!(EA[f] > 0.0) || !std::isfinite(EA[f]))
+                return fail(DR_E_INVALID, "problem %d fiber %d: EA must be finite and > 0 (got %g)",
+                            p, f, EA[f]);
+            const double dx = X[3 * b] - X[3 * a], dy = X[3 * b + 1] - X[3 * a + 1],
+                         dz = X[3 * b + 2] - X[3 * a + 2];
+            L2[f] = dx * dx + dy * dy + dz * dz;
+            L[f] = std::sqrt(L2[f]);
+            if (!(L[f] > 0.0))
+                return fail(DR_E_INVALID, "problem %d fiber %d has zero reference length", p, f);
+            ++degree[a];
+            ++degree[b];
+        }
+        int32_t n_free = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            if (!fixed[i]) {
+                ++n_free;
+                if (degree[i] == 0)
+                    return fail(DR_E_INVALID, "problem %d node %d is free but has no fiber", p, i);
+            }
+        }
+        // CSR node -> fibers in ascending fiber id
+        std::vector<int32_t> rp(N + 1, 0), ent(2 * (size_t)M);
+        for (int32_t i = 0; i < N; ++i) rp[i + 1] = rp[i] + degree[i];
+        {
+            std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+            for (int32_t f = 0; f < M; ++f) {
+                ent[fill[fib[2 * f]]++] = f;
+                ent[fill[fib[2 * f + 1]]++] = f;
+            }
+        }
+        // lumped mass (half the length of every fiber at the node) and the
+        // Gershgorin frequency bound, both summed in ascending fiber order
+        std::vector<double> m(N, 0.0), ksum(N, 0.0);
+        for (int32_t f = 0; f < M; ++f) {
+            const int32_t a = fib[2 * f], b = fib[2 * f + 1];
+            m[a] += 0.5 * L[f];
+            m[b] += 0.5 * L[f];
+            const double kh = 1.1 * EA[f] / L[f];
+            ksum[a] += kh;
+            ksum[b] += kh;
+        }
+        double w2 = 0.0, ea_sum = 0.0;
+        int32_t n_fixed = 0;
+        for (int32_t i = 0; i < N; ++i) {
+            if (fixed[i]) { ++n_fixed; continue; }
+            const double wi = 2.0 / m[i] * ksum[i];
+            if (wi > w2) w2 = wi;
+        }
+        for (int32_t f = 0; f < M; ++f) ea_sum += EA[f];
+        const double w = std::sqrt(w2);
+        ProbDesc &d = pk.desc[p];
+        std::memset(&d, 0, sizeof d);
+        d.N = N;
+        d.N_free = n_free;
+        d.M = M;
+        d.n_slices = (N + drk::kWave - 1) / drk::kWave;
+        d.dt = w > 0.0 ? opt->dt_safety * 2.0 / w : 0.0;
+        d.c = opt->damping * w;
+        const double ea_mean = M > 0 ? ea_sum / M : 0.0;
+        d.s_floor = 1e-4 * ea_mean * std::sqrt(3.0 * (n_fixed > 1 ? n_fixed : 1));
+
+        // renumber: free block then prescribed block; degree descending, then Morton
+        std::vector<int32_t> order(N);
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<uint32_t> key(N);
+        for (int32_t i = 0; i < N; ++i) key[i] = morton3(X + 3 * i);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t i, int32_t j) {
+            if ((fixed[i] != 0) != (fixed[j] != 0)) return fixed[i] == 0;
+            if (degree[i] != degree[j]) return degree[i] > degree[j];
+            return key[i] < key[j];
+        });
+        HostProblem &h = pk.hp[p];
+        h.N = N;
+        h.N_free = n_free;
+        h.M = M;
+        h.in_node_base = no[p];
+        h.new_of_old.assign(N, 0);
+        for (int32_t r = 0; r < N; ++r) h.new_of_old[order[r]] = r;
+
+        d.node_base = node_base;
+        d.slice_base = slice_base;
+        d.inc_base = inc_base;
+        for (int32_t r = 0; r < N; ++r) {
+            const int32_t i = order[r];
+            for (int a = 0; a < 3; ++a) pk.X[3 * (node_base + r) + a] = X[3 * i + a];
+            pk.mass[node_base + r] = m[i];
+            pk.invm[node_base + r] = 1.0 / m[i];
+            pk.deg[node_base + r] = degree[i];
+        }
+        if (N > pk.n_max) pk.n_max = N;
+        // sliced ELL incidences
+        int64_t off = 0;
+        for (int32_t q = 0; q < d.n_slices; ++q) {
+            int32_t width = 0;
+            for (int32_t lane = 0; lane < drk::kWave; ++lane) {
+                const int32_t r = q * drk::kWave + lane;
+                if (r < N) width = std::max(width, degree[order[r]]);
+            }
+            pk.slice_w.push_back(width);
+            pk.slice_off.push_back(off);
+            const size_t base = pk.nbr.size();
+            pk.nbr.resize(base + (size_t)width * drk::kWave, 0);
+            pk.kl.resize(base + (size_t)width * drk::kWave, KL{0.0, 0.0});
+            for (int32_t lane = 0; lane < drk::kWave; ++lane) {
+                const int32_t r = q * drk::kWave + lane;
+                if (r >= N) continue;
+                const int32_t i = order[r];
+                for (int32_t k = 0; k < degree[i]; ++k) {
+                    const int32_t f = ent[rp[i] + k];
+                    const int32_t other = fib[2 * f] == i ? fib[2 * f + 1] : fib[2 * f];
+                    const size_t e = base + (size_t)k * drk::kWave + lane;
+                    pk.nbr[e] = h.new_of_old[other];
+                    pk.kl[e] = KL{EA[f] / (2.0 * L2[f]), L2[f]};
+                }
+            }
+            off += (int64_t)width * drk::kWave;
+        }
+        slice_base += d.n_slices;
+        inc_base += off;
+        node_base += N;
+    }
+    return DR_OK;
+}
+
+template <class T> dr_status dev_upload(T **dst, const std::vector<T> &src, hipStream_t st)
+{
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    HIPCHECK(hipMalloc(reinterpret_cast<void **>(dst), bytes));
+    if (!src.empty())
+        HIPCHECK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return DR_OK;
+}
+
+template <class T> dr_status dev_zeros(T **dst, size_t n, hipStream_t st)
+{
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    HIPCHECK(hipMalloc(reinterpret_cast<void **>(dst), bytes));
+    HIPCHECK(hipMemsetAsync(*dst, 0, bytes, st));
+    return DR_OK;
+}
+
+dr_status create_device(dr_batch *b, Packed &pk)
+{
+    hipStream_t st = b->stream;
+    HIPCHECK(hipGetDevice(&b->device));
+    dr_status s;
+#define UP(dst, vec)                                                                              \
+    if ((s = dev_upload(&b->dst, pk.vec, st)) != DR_OK) return s;
+    UP(d_probs, desc)
+    UP(d_X, X)
+    UP(d_invm, invm)
+    UP(d_mass, mass)
+    UP(d_deg, deg)
+    UP(d_slice_w, slice_w)
+    UP(d_slice_off, slice_off)
+    UP(d_nbr, nbr)
+    UP(d_kl, kl)
+#undef UP
+    const size_t P = (size_t)b->P, nodes = (size_t)b->total_nodes;
+#define ZS(dst, n)                                                                                \
+    if ((s = dev_zeros(&b->dst, (n), st)) != DR_OK) return s;
+    ZS(d_u, 3 * nodes)
+    ZS(d_F_last, 9 * P)
+    ZS(d_has_state, P)
+    ZS(d_xg, 4 * nodes)
+    ZS(d_wg, 4 * nodes)
+    ZS(d_F, 9 * P)
+    ZS(d_ids, P)
+    ZS(d_order, P)
+    ZS(d_sigma, 9 * P)
+    ZS(d_sigma_fib, 9 * P)
+    ZS(d_rho, P)
+    ZS(d_ke, P)
+    ZS(d_iters, P)
+    ZS(d_status, P)
+    ZS(d_partial, 3 * ((size_t)pk.n_max / 256 + 2))
+    ZS(d_scalars, 8)
+#undef ZS
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_F), 9 * P * sizeof(double), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_ids), P * sizeof(int32_t), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_order), P * sizeof(int32_t), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_scalars), 8 * sizeof(double), 0));
+    HIPCHECK(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
+    HIPCHECK(hipStreamSynchronize(st));
+    return DR_OK;
+}
+
+// Launch shape for a solve whose largest problem has n_max nodes.  Returns
+// npt = -1 when DR_PLACE_LDS was asked for and the problem does not fit.
+LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
+{
+    LaunchPlan pl{};
+    const int block = opt.block;
+    auto reg_lds = [](int blk, int n) { return ((blk / drk::kWave) * 20 + 3 * n) * 8; };
+    // register-resident variant when the positions fit in LDS
+    int blk = block;
+    if (blk == 0) blk = n_max > 2048 ? 1024 : (n_max > 256 ? 512 : 256);
+    int npt = (n_max + blk - 1) / blk;
+    if (block == 0 && npt > kMaxNpt) {
+        blk = 1024;
+        npt = (n_max + blk - 1) / blk;
+    }
+    const bool fits = npt <= kMaxNpt && reg_lds(blk, n_max) <= kLdsLimit;
+    if (opt.placement == DR_PLACE_LDS && !fits) {
+        pl.block = blk;
+        pl.npt = -1;
+        return pl;
+    }
+    if (fits && opt.placement != DR_PLACE_GLOBAL) {
+        pl.block = blk;
+        pl.npt = npt < 1 ? 1 : npt;
+        pl.lds_bytes = reg_lds(blk, n_max);
+        return pl;
+    }
+    pl.block = block ? block : 1024;
+    pl.npt = 0;
+    pl.lds_bytes = (pl.block / drk::kWave) * 20 * 8;
+    return pl;
+}
+
+SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, bool with_ids, bool with_order)
+{
+    SolveArgs a{};
+    a.probs = b->d_probs;
+    a.ids = with_ids ? b->d_ids : nullptr;
+    a.order = with_order ? b->d_order : nullptr;
+    a.F = b->d_F;
+    a.n_solve = n_solve;
+    a.start = start;
+    a.tol = b->opt.tol;
+    a.max_iter = b->opt.max_iter;
+    a.X = b->d_X;
+    a.invm = b->d_invm;
+    a.mass = b->d_mass;
+    a.deg = b->d_deg;
+    a.slice_w = b->d_slice_w;
+    a.slice_off = b->d_slice_off;
+    a.nbr = b->d_nbr;
+    a.kl = b->d_kl;
+    a.u = b->d_u;
+    a.F_last = b->d_F_last;
+    a.has_state = b->d_has_state;
+    a.xg = b->d_xg;
+    a.wg = b->d_wg;
+    a.sigma = b->d_sigma;
+    a.sigma_fib = b->d_sigma_fib;
+    a.iters = b->d_iters;
+    a.rho = b->d_rho;
+    a.ke = b->d_ke;
+    a.status = b->d_status;
+    return a;
+}
+
+dr_status check_solve_args(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
+                           int32_t start)
+{
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    if (!F) return fail(DR_E_INVALID, "F is NULL");
+    if (start < DR_START_AFFINE || start > DR_START_WARM)
+        return fail(DR_E_INVALID, "start mode %d is not a dr_start value", start);
+    if (n_ids < 1 || n_ids > b->P)
+        return fail(DR_E_INVALID, "n_ids must be in [1, %d] (got %d)", b->P, n_ids);
+    if (!ids && n_ids != b->P)
+        return fail(DR_E_INVALID, "ids is NULL but n_ids (%d) != n_problems (%d)", n_ids, b->P);
+    if (ids) {
+        std::vector<char> seen(b->P, 0);
+        for (int32_t k = 0; k < n_ids; ++k) {
+            if (ids[k] < 0 || ids[k] >= b->P)
+                return fail(DR_E_INVALID, "ids[%d] = %d is out of range", k, ids[k]);
+            if (seen[ids[k]]) return fail(DR_E_INVALID, "ids[%d] = %d is repeated", k, ids[k]);
+            seen[ids[k]] = 1;
+        }
+    }
+    for (int64_t k = 0; k < 9LL * n_ids; ++k)
+        if (!std::isfinite(F[k])) return fail(DR_E_INVALID, "F[%lld] is not finite", (long long)k);
+    for (int32_t k = 0; k < n_ids; ++k) {
+        const double *f = F + 9 * (int64_t)k;
+        const double J = f[0] * (f[4] * f[8] - f[5] * f[7]) - f[1] * (f[3] * f[8] - f[5] * f[6]) +
+                         f[2] * (f[3] * f[7] - f[4] * f[6]);
+        if (!(J > 0.0)) return fail(DR_E_INVALID, "det F of solve %d is not > 0 (%g)", k, J);
+    }
+    return DR_OK;
+}
+
+// Stages F and ids, sorts the slots largest-first and uploads them.
+dr_status stage_solve(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids)
+{
+    HIPCHECK(hipEventSynchronize(b->staged)); // previous staging consumed
+    std::memcpy(b->h_F, F, 9 * sizeof(double) * (size_t)n_ids);
+    b->last_ids.resize(n_ids);
+    for (int32_t k = 0; k < n_ids; ++k) {
+        b->h_ids[k] = ids ? ids[k] : k;
+        b->last_ids[k] = b->h_ids[k];
+        b->h_order[k] = k;
+    }
+    std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
+        return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
+    });
+    HIPCHECK(hipMemcpyAsync(b->d_F, b->h_F, 9 * sizeof(double) * (size_t)n_ids,
+                            hipMemcpyHostToDevice, b->stream));
+    HIPCHECK(hipMemcpyAsync(b->d_ids, b->h_ids, sizeof(int32_t) * (size_t)n_ids,
+                            hipMemcpyHostToDevice, b->stream));
+    HIPCHECK(hipMemcpyAsync(b->d_order, b->h_order, sizeof(int32_t) * (size_t)n_ids,
+                            hipMemcpyHostToDevice, b->stream));
+    HIPCHECK(hipEventRecord(b->staged, b->stream));
+    return DR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+void dr_options_default(dr_options *o)
+{
+    if (!o) return;
+    o->precision = DR_FP64;
+    o->tol = 1e-8;
+    o->max_iter = 2000000;
+    o->damping = 1e-3;
+    o->dt_safety = 0.9;
+    o->block = 0;
+    o->placement = DR_PLACE_AUTO;
+}
+
+const char *dr_last_error(void) { return g_err.c_str(); }
+
+dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt, void *hip_stream,
+                          dr_batch **out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(DR_E_INVALID, "out is NULL");
+        *out = nullptr;
+        dr_status s = validate_options(opt);
+        if (s != DR_OK) return s;
+        Packed pk;
+        s = pack(nets, opt, pk);
+        if (s != DR_OK) return s;
+        if (plan_for(*opt, pk.n_max).npt < 0)
+            return fail(DR_E_INVALID,
+                        "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
+                        pk.n_max, opt->block);
+        dr_batch *b = new dr_batch();
+        b->opt = *opt;
+        b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        b->P = nets->n_problems;
+        b->total_nodes = nets->node_offsets[b->P];
+        b->total_fibers = nets->fiber_offsets[b->P];
+        b->total_slices = (int64_t)pk.slice_w.size();
+        b->total_inc = (int64_t)pk.nbr.size();
+        b->n_max = pk.n_max;
+        b->plan = plan_for(*opt, pk.n_max);
+        b->desc = pk.desc;
+        s = create_device(b, pk);
+        if (s != DR_OK) {
+            free_all(b);
+            delete b;
+            return s;
+        }
+        b->hp = std::move(pk.hp);
+        *out = b;
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_batch_create");
+    }
+}
+
+dr_status dr_solve(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids, int32_t start)
+{
+    try {
+        g_err.clear();
+        dr_status s = check_solve_args(b, F, ids, n_ids, start);
+        if (s != DR_OK) return s;
+        s = stage_solve(b, F, ids, n_ids);
+        if (s != DR_OK) return s;
+        const SolveArgs a = make_args(b, n_ids, start, true, true);
+        const int rc = drk::launch_solve(a, b->plan, b->stream);
+        if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+        b->last_n = n_ids;
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_solve");
+    }
+}
+
+dr_status dr_solve_device(dr_batch *b, const double *F_device, const int32_t *ids_device,
+                          int32_t n_ids, int32_t start)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!F_device) return fail(DR_E_INVALID, "F_device is NULL");
+        if (start < DR_START_AFFINE || start > DR_START_WARM)
+            return fail(DR_E_INVALID, "start mode %d is not a dr_start value", start);
+        if (n_ids < 1 || n_ids > b->P)
+            return fail(DR_E_INVALID, "n_ids must be in [1, %d] (got %d)", b->P, n_ids);
+        if (!ids_device && n_ids != b->P)
+            return fail(DR_E_INVALID, "ids_device is NULL but n_ids != n_problems");
+        SolveArgs a = make_args(b, n_ids, start, false, false);
+        a.F = F_device;
+        a.ids = ids_device;
+        const int rc = drk::launch_solve(a, b->plan, b->stream);
+        if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+        b->last_n = n_ids;
+        b->last_ids.clear(); // unknown on the host
+        return DR_OK;
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_solve_device");
+    }
+}
+
+dr_status dr_sync(dr_batch *b)
+{
+    g_err.clear();
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    return DR_OK;
+}
+
+dr_status dr_stress(dr_batch *b, double *sigma, double *sigma_fib, double *u, int32_t *result,
+                    int64_t *iters, double *resid, double *ke)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (b->last_n < 0) return fail(DR_E_STATE, "dr_stress called before any dr_solve");
+        const size_t n = (size_t)b->last_n;
+        hipStream_t st = b->stream;
+        if (sigma) HIPCHECK(hipMemcpyAsync(sigma, b->d_sigma, 9 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (sigma_fib)
+            HIPCHECK(hipMemcpyAsync(sigma_fib, b->d_sigma_fib, 9 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (result) HIPCHECK(hipMemcpyAsync(result, b->d_status, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (iters) HIPCHECK(hipMemcpyAsync(iters, b->d_iters, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        if (resid) HIPCHECK(hipMemcpyAsync(resid, b->d_rho, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (ke) HIPCHECK(hipMemcpyAsync(ke, b->d_ke, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        std::vector<double> ur;
+        if (u) {
+            ur.resize(3 * (size_t)b->total_nodes);
+            HIPCHECK(hipMemcpyAsync(ur.data(), b->d_u, ur.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+        if (u) {
+            for (int32_t p = 0; p < b->P; ++p) {
+                const HostProblem &h = b->hp[p];
+                const int64_t nb = b->desc[p].node_base;
+                for (int32_t i = 0; i < h.N; ++i) {
+                    const int64_t src = 3 * (nb + h.new_of_old[i]);
+                    const int64_t dst = 3 * (h.in_node_base + i);
+                    u[dst] = ur[src];
+                    u[dst + 1] = ur[src + 1];
+                    u[dst + 2] = ur[src + 2];
+                }
+            }
+        }
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_stress");
+    }
+}
+
+dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
+                        int32_t start)
+{
+    try {
+        g_err.clear();
+        dr_status s = check_solve_args(b, F, ids, n_ids, start);
+        if (s != DR_OK) return s;
+        s = stage_solve(b, F, ids, n_ids);
+        if (s != DR_OK) return s;
+        const SolveArgs a = make_args(b, n_ids, start, true, false);
+        hipStream_t st = b->stream;
+        for (int32_t slot = 0; slot < n_ids; ++slot) {
+            const ProbDesc &d = b->desc[b->h_ids[slot]];
+            int rc = drk::launch_loop_iteration_kernels(a, slot, 0, d.N, b->d_partial, b->d_scalars,
+                                                        0, st);
+            if (rc != 0) return fail(DR_E_DEVICE, "loop set-up launch failed: %s", drk::kernel_error_string(rc));
+            int64_t n = 0;
+            double rho = 0.0, ke = 0.0;
+            int status = DR_MAX_ITER;
+            for (;;) {
+                rc = drk::launch_loop_iteration_kernels(a, slot, 1, d.N, b->d_partial, b->d_scalars,
+                                                        n, st);
+                if (rc != 0) return fail(DR_E_DEVICE, "loop pass launch failed: %s", drk::kernel_error_string(rc));
+                HIPCHECK(hipMemcpyAsync(b->h_scalars, b->d_scalars, 3 * sizeof(double),
+                                        hipMemcpyDeviceToHost, st));
+                HIPCHECK(hipStreamSynchronize(st));
+                ++n;
+                double den = std::sqrt(b->h_scalars[1]);
+                if (den < d.s_floor) den = d.s_floor;
+                rho = std::sqrt(b->h_scalars[0]) / den;
+                ke = 0.5 * b->h_scalars[2];
+                if (!std::isfinite(rho) || !std::isfinite(ke)) { status = DR_NONFINITE; break; }
+                if (rho <= b->opt.tol) { status = DR_CONVERGED; break; }
+                if (n >= b->opt.max_iter) { status = DR_MAX_ITER; break; }
+            }
+            double sc[8] = {0, 0, 0, rho, ke, (double)status, 0, 0};
+            rc = drk::launch_loop_iteration_kernels(a, slot, 2, d.N, b->d_partial, sc, n, st);
+            if (rc != 0) return fail(DR_E_DEVICE, "loop stress launch failed: %s", drk::kernel_error_string(rc));
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+        b->last_n = n_ids;
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_solve_loop");
+    }
+}
+
+dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_nodes,
+                        int64_t *total_fibers, int32_t *block, int32_t *lds_bytes,
+                        int32_t *nodes_per_thread)
+{
+    g_err.clear();
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    const LaunchPlan &pl = b->plan;
+    if (n_problems) *n_problems = b->P;
+    if (total_nodes) *total_nodes = b->total_nodes;
+    if (total_fibers) *total_fibers = b->total_fibers;
+    if (block) *block = pl.block;
+    if (lds_bytes) *lds_bytes = pl.lds_bytes;
+    if (nodes_per_thread) *nodes_per_thread = pl.npt;
+    return DR_OK;
+}
+
+dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor)
+{
+    g_err.clear();
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    for (int32_t p = 0; p < b->P; ++p) {
+        if (dt) dt[p] = b->desc[p].dt;
+        if (c) c[p] = b->desc[p].c;
+        if (s_floor) s_floor[p] = b->desc[p].s_floor;
+    }
+    return DR_OK;
+}
+
+void dr_batch_destroy(dr_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    free_all(b);
+    delete b;
+}
+
+} // extern "C"

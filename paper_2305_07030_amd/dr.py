@@ -1,0 +1,278 @@
+"""ctypes binding of libdr (include/dr.h): argument marshalling only.
+
+Every step of a solve runs in libdr's HIP kernels; this module converts
+numpy arrays / torch tensors to pointers and back.  It raises if libdr.so is
+missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+DR_OK, DR_E_INVALID, DR_E_NOMEM, DR_E_DEVICE, DR_E_STATE = 0, -1, -2, -3, -4
+DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE = 0, 1, 2
+DR_FP64, DR_FP32 = 0, 1
+DR_START_AFFINE, DR_START_ZERO, DR_START_WARM = 0, 1, 2
+DR_PLACE_AUTO, DR_PLACE_LDS, DR_PLACE_GLOBAL = 0, 1, 2
+
+_STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
+                 DR_E_DEVICE: "DR_E_DEVICE", DR_E_STATE: "DR_E_STATE"}
+
+# Every exported symbol of include/dr.h.
+EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
+           "dr_stress", "dr_sync", "dr_solve_loop", "dr_batch_info", "dr_batch_scalars",
+           "dr_batch_destroy", "dr_last_error")
+
+
+class DrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dr_networks(C.Structure):
+    _fields_ = [("n_problems", C.c_int32),
+                ("node_offsets", C.POINTER(C.c_int64)),
+                ("fiber_offsets", C.POINTER(C.c_int64)),
+                ("X", C.POINTER(C.c_double)),
+                ("fiber_nodes", C.POINTER(C.c_int32)),
+                ("EA", C.POINTER(C.c_double)),
+                ("fixed", C.POINTER(C.c_uint8))]
+
+
+class dr_options(C.Structure):
+    _fields_ = [("precision", C.c_int32),
+                ("tol", C.c_double),
+                ("max_iter", C.c_int64),
+                ("damping", C.c_double),
+                ("dt_safety", C.c_double),
+                ("block", C.c_int32),
+                ("placement", C.c_int32)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load():
+    """Loads libdr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2305_07030_amd.build.build()")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.dr_options_default.argtypes = [C.POINTER(dr_options)]
+    lib.dr_options_default.restype = None
+    lib.dr_batch_create.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options), vp, C.POINTER(vp)]
+    lib.dr_batch_create.restype = C.c_int
+    lib.dr_solve.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_solve.restype = C.c_int
+    lib.dr_solve_device.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_solve_device.restype = C.c_int
+    lib.dr_stress.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.dr_stress.restype = C.c_int
+    lib.dr_sync.argtypes = [vp]
+    lib.dr_sync.restype = C.c_int
+    lib.dr_solve_loop.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_solve_loop.restype = C.c_int
+    lib.dr_batch_info.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.dr_batch_info.restype = C.c_int
+    lib.dr_batch_scalars.argtypes = [vp, vp, vp, vp]
+    lib.dr_batch_scalars.restype = C.c_int
+    lib.dr_batch_destroy.argtypes = [vp]
+    lib.dr_batch_destroy.restype = None
+    lib.dr_last_error.argtypes = []
+    lib.dr_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != DR_OK:
+        raise DrError(rc, load().dr_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def dr_options_default() -> dr_options:
+    o = dr_options()
+    load().dr_options_default(C.byref(o))
+    return o
+
+
+def make_options(**kw) -> dr_options:
+    o = dr_options_default()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+def pack_networks(packed: dict):
+    """dr_networks view of Batch.packed() arrays (the arrays are kept alive)."""
+    arrs = dict(
+        node_offsets=np.ascontiguousarray(packed["node_offsets"], np.int64),
+        fiber_offsets=np.ascontiguousarray(packed["fiber_offsets"], np.int64),
+        X=np.ascontiguousarray(packed["X"], np.float64),
+        fiber_nodes=np.ascontiguousarray(packed["fiber_nodes"], np.int32),
+        EA=np.ascontiguousarray(packed["EA"], np.float64),
+        fixed=np.ascontiguousarray(packed["fixed"], np.uint8),
+    )
+    n = dr_networks()
+    n.n_problems = len(arrs["node_offsets"]) - 1
+    n.node_offsets = arrs["node_offsets"].ctypes.data_as(C.POINTER(C.c_int64))
+    n.fiber_offsets = arrs["fiber_offsets"].ctypes.data_as(C.POINTER(C.c_int64))
+    n.X = arrs["X"].ctypes.data_as(C.POINTER(C.c_double))
+    n.fiber_nodes = arrs["fiber_nodes"].ctypes.data_as(C.POINTER(C.c_int32))
+    n.EA = arrs["EA"].ctypes.data_as(C.POINTER(C.c_double))
+    n.fixed = arrs["fixed"].ctypes.data_as(C.POINTER(C.c_uint8))
+    return n, arrs
+
+
+def dr_batch_create(packed: dict, opt: dr_options, stream=None) -> int:
+    """Returns the opaque handle (an int)."""
+    lib = load()
+    nets, keep = pack_networks(packed)
+    h = C.c_void_p()
+    _check(lib.dr_batch_create(C.byref(nets), C.byref(opt), stream, C.byref(h)))
+    del keep
+    return h.value
+
+
+def dr_solve(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int = DR_START_AFFINE):
+    F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_solve(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
+
+
+def dr_solve_device(h: int, F_device_ptr: int, ids_device_ptr: Optional[int], n_ids: int,
+                    start: int = DR_START_AFFINE):
+    _check(load().dr_solve_device(h, F_device_ptr, ids_device_ptr, int(n_ids), int(start)))
+
+
+def dr_solve_loop(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int = DR_START_AFFINE):
+    F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_solve_loop(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
+
+
+def dr_stress(h: int, n_ids: int, total_nodes: Optional[int] = None, want_u: bool = False) -> dict:
+    sig = np.zeros((n_ids, 9)); sigf = np.zeros((n_ids, 9))
+    res = np.zeros(n_ids, np.int32); it = np.zeros(n_ids, np.int64)
+    rho = np.zeros(n_ids); ke = np.zeros(n_ids)
+    u = np.zeros((total_nodes, 3)) if want_u else None
+    _check(load().dr_stress(h, _ptr(sig), _ptr(sigf), _ptr(u), _ptr(res), _ptr(it), _ptr(rho), _ptr(ke)))
+    return dict(sigma=sig.reshape(n_ids, 3, 3), sigma_fib=sigf.reshape(n_ids, 3, 3), u=u,
+                result=res, iters=it, rho=rho, ke=ke)
+
+
+def dr_sync(h: int):
+    _check(load().dr_sync(h))
+
+
+def dr_batch_info(h: int) -> dict:
+    a = C.c_int32(); b = C.c_int64(); c = C.c_int64(); d = C.c_int32(); e = C.c_int32(); f = C.c_int32()
+    _check(load().dr_batch_info(h, C.addressof(a), C.addressof(b), C.addressof(c), C.addressof(d),
+                                C.addressof(e), C.addressof(f)))
+    return dict(n_problems=a.value, total_nodes=b.value, total_fibers=c.value, block=d.value,
+                lds_bytes=e.value, nodes_per_thread=f.value)
+
+
+def dr_batch_scalars(h: int, n_problems: int) -> dict:
+    dt = np.zeros(n_problems); c = np.zeros(n_problems); fl = np.zeros(n_problems)
+    _check(load().dr_batch_scalars(h, _ptr(dt), _ptr(c), _ptr(fl)))
+    return dict(dt=dt, c=c, s_floor=fl)
+
+
+def dr_batch_destroy(h: int):
+    load().dr_batch_destroy(h)
+
+
+def dr_last_error() -> str:
+    return load().dr_last_error().decode()
+
+
+def current_stream():
+    """The current torch HIP stream as a raw pointer (None without a GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class DRBatch:
+    """Owns one dr_batch handle for a paper_2305_07030_amd.inputs.Batch."""
+
+    def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
+                 block=0, placement=DR_PLACE_AUTO, precision=DR_FP64, stream=None):
+        self.batch = batch
+        self.P = len(batch)
+        self.total_nodes = batch.total_nodes
+        self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
+                                dt_safety=dt_safety, block=block, placement=placement)
+        self.h = dr_batch_create(batch.packed(), self.opt, stream if stream is not None else current_stream())
+        self._n_last = None
+
+    def solve(self, F=None, ids=None, start=DR_START_AFFINE):
+        if F is None:
+            F = self.batch.F if ids is None else self.batch.F[np.asarray(ids)]
+        F = np.asarray(F).reshape(-1, 9)
+        dr_solve(self.h, F, ids, start)
+        self._n_last = F.shape[0]
+
+    def solve_loop(self, F=None, ids=None, start=DR_START_AFFINE):
+        if F is None:
+            F = self.batch.F if ids is None else self.batch.F[np.asarray(ids)]
+        F = np.asarray(F).reshape(-1, 9)
+        dr_solve_loop(self.h, F, ids, start)
+        self._n_last = F.shape[0]
+
+    def solve_device(self, F_dev, ids_dev=None, start=DR_START_AFFINE):
+        n = int(F_dev.shape[0])
+        dr_solve_device(self.h, F_dev.data_ptr(), None if ids_dev is None else ids_dev.data_ptr(), n, start)
+        self._n_last = n
+
+    def results(self, want_u=False) -> dict:
+        if self._n_last is None:
+            raise DrError(DR_E_STATE, "no solve yet")
+        r = dr_stress(self.h, self._n_last, self.total_nodes, want_u)
+        if want_u:
+            no = self.batch.packed()["node_offsets"]
+            r["u_list"] = [r["u"][no[i]:no[i + 1]] for i in range(self.P)]
+        return r
+
+    def sync(self):
+        dr_sync(self.h)
+
+    def info(self) -> dict:
+        return dr_batch_info(self.h)
+
+    def scalars(self) -> dict:
+        return dr_batch_scalars(self.h, self.P)
+
+    def close(self):
+        if self.h:
+            dr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dr.h, and rejects invalid input (validation runs before
+any HIP call, so these run on a CPU-only machine)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2305_07030_amd import build as B
+from paper_2305_07030_amd import dr
+from paper_2305_07030_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "dr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(dr_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if B.stale():
+        B.build()
+    return dr.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = header_functions()
+    assert len(names) >= 11
+    assert set(names) == set(dr.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(\w+)$", out, flags=re.M))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_options_default(lib):
+    o = dr.dr_options_default()
+    assert (o.precision, o.tol, o.max_iter, o.damping, o.dt_safety, o.block, o.placement) == \
+        (dr.DR_FP64, 1e-8, 2000000, 1e-3, 0.9, 0, dr.DR_PLACE_AUTO)
+
+
+def _packed():
+    return I.small_batch(3, 40, 60, 0.01, seed=3).packed()
+
+
+def _expect_invalid(pk, opt=None, match=""):
+    with pytest.raises(dr.DrError) as e:
+        dr.dr_batch_create(pk, opt or dr.dr_options_default())
+    assert e.value.status == dr.DR_E_INVALID
+    assert match in str(e.value), str(e.value)
+
+
+def test_rejects_bad_networks(lib):
+    pk = _packed()
+    bad = dict(pk); bad["EA"] = pk["EA"].copy(); bad["EA"][7] = np.nan
+    _expect_invalid(bad, match="problem 0 fiber 7")
+    bad = dict(pk); bad["EA"] = pk["EA"].copy(); bad["EA"][pk["fiber_offsets"][1] + 2] = 0.0
+    _expect_invalid(bad, match="problem 1 fiber 2")
+    bad = dict(pk); bad["fiber_nodes"] = pk["fiber_nodes"].copy(); bad["fiber_nodes"][4, 1] = 999
+    _expect_invalid(bad, match="out of range")
+    bad = dict(pk); bad["fiber_nodes"] = pk["fiber_nodes"].copy()
+    bad["fiber_nodes"][5, 1] = bad["fiber_nodes"][5, 0]
+    _expect_invalid(bad, match="to itself")
+    bad = dict(pk); bad["X"] = pk["X"].copy(); bad["X"][3, 2] = np.inf
+    _expect_invalid(bad, match="not finite")
+    # a zero-length fiber
+    bad = dict(pk); bad["X"] = pk["X"].copy()
+    a, b = pk["fiber_nodes"][0]
+    bad["X"][b] = bad["X"][a]
+    _expect_invalid(bad, match="zero reference length")
+    # a free node without fibers
+    net = I.Network(np.random.default_rng(0).random((4, 3)), np.array([[0, 1], [1, 2]], np.int32),
+                    np.ones(2), np.array([1, 0, 1, 0], np.uint8))
+    _expect_invalid(I.Batch([net], np.eye(3)[None]).packed(), match="node 3 is free but has no fiber")
+    bad = dict(pk); bad["node_offsets"] = pk["node_offsets"].copy(); bad["node_offsets"][2] = bad["node_offsets"][1]
+    _expect_invalid(bad, match="has no nodes")
+
+
+def test_rejects_bad_options(lib):
+    pk = _packed()
+    for field, value, msg in [("tol", 0.0, "tol"), ("max_iter", 0, "max_iter"),
+                              ("damping", -1.0, "damping"), ("dt_safety", 1.5, "dt_safety"),
+                              ("block", 128, "block"), ("placement", 7, "placement"),
+                              ("precision", 5, "precision")]:
+        o = dr.dr_options_default()
+        setattr(o, field, value)
+        _expect_invalid(pk, o, msg)
+    # LDS placement cannot hold a 7000-node problem
+    big = I.Batch([I.draw_network(np.random.default_rng(1), 7000)], np.eye(3)[None]).packed()
+    o = dr.dr_options_default(); o.placement = dr.DR_PLACE_LDS
+    _expect_invalid(big, o, "DR_PLACE_LDS")
+
+
+def test_null_arguments(lib):
+    import ctypes as C
+    o = dr.dr_options_default()
+    h = C.c_void_p()
+    assert lib.dr_batch_create(None, C.byref(o), None, C.byref(h)) == dr.DR_E_INVALID
+    assert "NULL" in dr.dr_last_error()
+    assert lib.dr_solve(None, None, None, 1, 0) == dr.DR_E_INVALID
+    assert lib.dr_stress(None, None, None, None, None, None, None, None) == dr.DR_E_INVALID
+    lib.dr_batch_destroy(None)  # ignored

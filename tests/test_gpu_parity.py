@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+The bar: FP64 stress within 1e-8 relative (Frobenius norm of the difference
+over the norm of the oracle's stress) after both ran the same iteration to
+the same tolerance; pass counts within +-1; displacements at a fixed pass
+count equal to round-off.  Inputs are the seeded synthetic networks of
+paper_2305_07030_amd.inputs.
+"""
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_07030_amd import dr
+from paper_2305_07030_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+S = 0.9
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dr.load()  # raises when libdr.so is missing: no fallback
+    O.build(force=False)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def oracle_all(batch, **kw):
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda i: O.solve(batch.nets[i], batch.F[i], dt_safety=S, **kw),
+                           range(len(batch))))
+
+
+def gpu_solve(batch, *, want_u=False, start=dr.DR_START_AFFINE, ids=None, **kw):
+    b = dr.DRBatch(batch, dt_safety=S, **kw)
+    b.solve(ids=ids, start=start)
+    r = b.results(want_u=want_u)
+    return b, r
+
+
+def test_single_network_parity():
+    batch = I.config_single()
+    say("single 500-node network, FP64, tol 1e-8, damping 1e-3")
+    b, g = gpu_solve(batch, tol=1e-8, damping=1e-3, want_u=True)
+    o = O.solve(batch.nets[0], batch.F[0], tol=1e-8, beta=1e-3, dt_safety=S)
+    say("iters gpu", g["iters"][0], "oracle", o.iters, "sigma rel", rel(g["sigma"][0], o.sigma))
+    assert g["result"][0] == dr.DR_CONVERGED and o.status == O.CONVERGED
+    assert abs(int(g["iters"][0]) - o.iters) <= 1
+    assert rel(g["sigma"][0], o.sigma) < 1e-8
+    assert rel(g["sigma_fib"][0], o.sigma_fib) < 1e-8
+    assert g["rho"][0] <= 1e-8
+    sc = b.scalars()
+    assert sc["dt"][0] == pytest.approx(o.dt, rel=1e-15) and sc["c"][0] == pytest.approx(o.c, rel=1e-15)
+
+
+@pytest.mark.parametrize("block,placement", [(256, dr.DR_PLACE_LDS), (512, dr.DR_PLACE_LDS),
+                                             (1024, dr.DR_PLACE_LDS), (256, dr.DR_PLACE_GLOBAL),
+                                             (1024, dr.DR_PLACE_GLOBAL)])
+def test_fixed_pass_count_parity(block, placement):
+    """Same number of passes on both sides (status MAX_ITER): the states must
+    agree to round-off, node by node.  Sizes span several slices, ragged
+    tails and (for block 256) several nodes per thread."""
+    batch = I.small_batch(6, 90, 700, 0.02, seed=21)
+    K = 1500
+    say(f"fixed {K} passes, block {block}, placement {placement}, N =", [n.n_nodes for n in batch.nets])
+    b, g = gpu_solve(batch, tol=1e-30, max_iter=K, damping=1e-3, block=block, placement=placement,
+                     want_u=True)
+    os_ = oracle_all(batch, tol=1e-30, max_iter=K, beta=1e-3)
+    for i, o in enumerate(os_):
+        assert g["result"][i] == dr.DR_MAX_ITER and o.status == O.MAX_ITER
+        assert g["iters"][i] == K == o.iters
+        err = np.abs(g["u_list"][i] - o.u).max()
+        assert err < 1e-11, (i, err)
+        assert rel(g["sigma"][i], o.sigma) < 1e-9
+        assert rel(g["sigma_fib"][i], o.sigma_fib) < 1e-9
+        assert g["rho"][i] == pytest.approx(o.rho, rel=1e-6)
+        assert g["ke"][i] == pytest.approx(o.ke, rel=1e-6)
+
+
+def test_small_batch_converged_parity():
+    batch = I.small_batch(12, 60, 650, 0.02, seed=22)
+    say("12 small networks to tol 1e-8, N =", [n.n_nodes for n in batch.nets])
+    b, g = gpu_solve(batch, tol=1e-8, damping=1e-3, want_u=True)
+    os_ = oracle_all(batch, tol=1e-8, beta=1e-3)
+    for i, o in enumerate(os_):
+        assert o.status == O.CONVERGED and g["result"][i] == dr.DR_CONVERGED
+        assert abs(int(g["iters"][i]) - o.iters) <= 1, (i, g["iters"][i], o.iters)
+        assert rel(g["sigma"][i], o.sigma) < 1e-8, (i, rel(g["sigma"][i], o.sigma))
+
+
+def test_uniform_batch_full_size_sampled():
+    """The 256-network batch (N uniform in 1000..5000) in the launch the
+    benchmark times; three networks are re-solved by the oracle, every
+    network is checked for properties that hold at any size."""
+    batch = I.config_uniform_batch(256)
+    say("256-network batch, FP64, damping 2.5e-4: GPU solve")
+    t = time.time()
+    b, g = gpu_solve(batch, tol=1e-8, damping=2.5e-4)
+    say(f"GPU solve done in {time.time() - t:.1f}s; iters min/median/max",
+        g["iters"].min(), int(np.median(g["iters"])), g["iters"].max())
+    info = b.info()
+    say("launch", info)
+    assert (g["result"] == dr.DR_CONVERGED).all()
+    assert (g["rho"] <= 1e-8).all()
+    for i in range(len(batch)):
+        s = g["sigma"][i]
+        assert np.linalg.norm(s - s.T) < 1e-5 * np.linalg.norm(s)
+        assert rel(g["sigma_fib"][i], s) < 1e-5
+    sizes = np.array([n.n_nodes for n in batch.nets])
+    sample = list(np.argsort(sizes)[:3])
+    say("oracle on networks", sample, "N =", sizes[sample])
+    sub = batch.subset(sample)
+    os_ = oracle_all(sub, tol=1e-8, beta=2.5e-4)
+    for k, i in enumerate(sample):
+        o = os_[k]
+        say(f"net {i}: iters gpu {g['iters'][i]} oracle {o.iters}, sigma rel {rel(g['sigma'][i], o.sigma):.2e}")
+        assert o.status == O.CONVERGED
+        assert abs(int(g["iters"][i]) - o.iters) <= 1
+        assert rel(g["sigma"][i], o.sigma) < 1e-8
+
+
+def test_loop_comparator_matches_persistent():
+    batch = I.small_batch(2, 80, 140, 0.02, seed=23)
+    say("launch-loop comparator vs persistent kernel, N =", [n.n_nodes for n in batch.nets])
+    b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
+    b.solve()
+    p = b.results(want_u=True)
+    b.solve_loop()
+    l = b.results(want_u=True)
+    for i in range(len(batch)):
+        assert l["result"][i] == dr.DR_CONVERGED
+        assert abs(int(l["iters"][i]) - int(p["iters"][i])) <= 1
+        assert rel(l["sigma"][i], p["sigma"][i]) < 1e-8
+    o = oracle_all(batch, tol=1e-8, beta=1e-3)
+    for i in range(len(batch)):
+        assert rel(l["sigma"][i], o[i].sigma) < 1e-8
+
+
+def test_closed_forms_on_gpu():
+    say("closed forms: single fiber, lattice from u = 0, identity, rotation")
+    # single fiber, both ends prescribed
+    X = np.array([[0.2, 0.3, 0.4], [0.7, 0.6, 0.5]])
+    net = I.Network(X, np.array([[0, 1]], np.int32), np.array([1.7]), np.array([1, 1], np.uint8))
+    F = np.array([[1.1, 0.05, 0.0], [0.02, 0.95, 0.03], [0.0, 0.01, 1.02]])
+    b, g = gpu_solve(I.Batch([net], F[None]), tol=1e-8)
+    x = X @ F.T
+    d = x[1] - x[0]
+    l = np.linalg.norm(d)
+    L = np.linalg.norm(X[1] - X[0])
+    sig = 1.7 * ((l / L) ** 2 - 1) / 2 * np.outer(d, d) / l / np.linalg.det(F)
+    assert g["iters"][0] == 1 and rel(g["sigma"][0], sig) < 1e-13
+    # lattice from u = 0 relaxes to the affine state
+    m = 3
+    lat = I.cubic_lattice(m, EA=1.3)
+    F = np.array([[1.05, 0.02, 0.0], [0.01, 1.03, 0.0], [0.0, 0.015, 1.04]])
+    b, g = gpu_solve(I.Batch([lat], F[None]), tol=1e-12, damping=0.02, start=dr.DR_START_ZERO,
+                     want_u=True)
+    J = np.linalg.det(F)
+    sig = sum((m + 1) ** 2 / J * 1.3 * (np.linalg.norm(F[:, k]) ** 2 - 1) / (2 * np.linalg.norm(F[:, k]))
+              * np.outer(F[:, k], F[:, k]) for k in range(3))
+    assert g["result"][0] == dr.DR_CONVERGED
+    assert np.abs(g["u"] - lat.X @ (F - np.eye(3)).T).max() < 1e-11
+    assert rel(g["sigma"][0], sig) < 1e-9
+    # no load, and a rigid rotation
+    base = I.config_single(200, seed=3)
+    R = I.random_rotation(np.random.default_rng(11))
+    b, g = gpu_solve(I.Batch([base.nets[0]] * 2, np.stack([np.eye(3), R])), tol=1e-8, want_u=True)
+    assert list(g["iters"]) == [1, 1]
+    assert np.array_equal(g["sigma"][0], np.zeros((3, 3)))
+    assert np.array_equal(g["u"][:200], np.zeros((200, 3)))
+    assert np.abs(g["sigma"][1]).max() < 1e-13
+
+
+def test_all_prescribed_and_max_iter():
+    say("all-prescribed problem, max_iter cap")
+    rng = np.random.default_rng(4)
+    net = I.complete_network(rng, 5, 5)
+    other = I.config_single(120, seed=9).nets[0]
+    F = np.stack([I.sym_perturbed_F(rng, 0.02)] * 2)
+    b, g = gpu_solve(I.Batch([net, other], F), tol=1e-8, max_iter=7)
+    o = O.solve(net, F[0], tol=1e-8, beta=1e-3, dt_safety=S)
+    assert g["result"][0] == dr.DR_CONVERGED and g["iters"][0] == 1
+    assert rel(g["sigma"][0], o.sigma) < 1e-13
+    assert g["result"][1] == dr.DR_MAX_ITER and g["iters"][1] == 7
+
+
+def test_warm_start_parity():
+    batch = I.small_batch(4, 100, 300, 0.02, seed=24)
+    rng = np.random.default_rng(5)
+    F2 = np.stack([F + (I.sym_perturbed_F(rng, 0.002) - np.eye(3)) for F in batch.F])
+    say("warm start: cold solve then warm solve with F + sym U(0.002)")
+    b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
+    b.solve()
+    cold = b.results()
+    b.solve(F=F2, start=dr.DR_START_WARM)
+    warm = b.results(want_u=True)
+    for i in range(len(batch)):
+        o1 = O.solve(batch.nets[i], batch.F[i], tol=1e-8, beta=1e-3, dt_safety=S)
+        o2 = O.solve(batch.nets[i], F2[i], tol=1e-8, beta=1e-3, dt_safety=S, start=O.START_WARM,
+                     F_prev=batch.F[i], u_prev=o1.u)
+        assert abs(int(warm["iters"][i]) - o2.iters) <= 1
+        assert rel(warm["sigma"][i], o2.sigma) < 1e-8
+        assert warm["iters"][i] < cold["iters"][i]
+
+
+def test_determinism_subsets_and_device_entry():
+    """Bitwise repeatability, the same result alone and in a batch (each
+    problem's arithmetic does not depend on the others), and the
+    device-pointer entry point equal to the host one."""
+    import torch
+    batch = I.small_batch(10, 100, 500, 0.02, seed=25)
+    say("determinism / subset / device entry, N =", [n.n_nodes for n in batch.nets])
+    b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
+    b.solve()
+    r1 = b.results(want_u=True)
+    b.solve()
+    r2 = b.results(want_u=True)
+    assert np.array_equal(r1["sigma"], r2["sigma"]) and np.array_equal(r1["u"], r2["u"])
+    ids = np.array([7, 2, 9], np.int32)
+    b.solve(ids=ids)
+    r3 = b.results()
+    assert np.array_equal(r3["sigma"], r1["sigma"][ids])
+    assert np.array_equal(r3["iters"], r1["iters"][ids])
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    b.solve_device(Fd)
+    r4 = b.results()
+    assert np.array_equal(r4["sigma"], r1["sigma"])
+    b.solve(ids=np.array([4], np.int32))
+    ra = b.results()
+    assert np.array_equal(ra["sigma"][0], r1["sigma"][4])
+    # a batch of its own may choose another launch shape: equal to round-off
+    alone = dr.DRBatch(batch.subset([4]), tol=1e-8, damping=1e-3, dt_safety=S)
+    alone.solve()
+    rb = alone.results()
+    assert abs(int(rb["iters"][0]) - int(r1["iters"][4])) <= 1
+    assert rel(rb["sigma"][0], r1["sigma"][4]) < 1e-8
