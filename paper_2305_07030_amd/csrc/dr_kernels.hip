@@ -82,6 +82,14 @@ __device__ __forceinline__ Row node_row(const SolveArgs &A, const ProbDesc &P, i
     return row;
 }
 
+// Squared length, rounded as the host rounds L^2 (no fused multiply-add), so
+// a fiber at its reference length carries exactly zero force.
+__device__ __forceinline__ double len2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
 // Internal force on node r (Fig. 1, getInternalForces): sum over the node's
 // fibers of T d / l with d = x_j - x_i and T = EA (l^2 / L^2 - 1) / 2
 // = k (l^2 - L^2), k = EA / (2 L^2).
@@ -100,7 +108,7 @@ __device__ __forceinline__ void gather_force(const SolveArgs &A, const Row &row,
             double xj, yj, zj;
             pos.load(j, xj, yj, zj);
             const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-            const double l2 = dx * dx + dy * dy + dz * dz;
+            const double l2 = len2(dx, dy, dz);
             const double s = c.k * (l2 - c.L2) * rsqrt(l2);
             gx += s * dx; gy += s * dy; gz += s * dz;
         }
@@ -125,7 +133,7 @@ __device__ __forceinline__ void gather_force_stress(const SolveArgs &A, const Ro
             double xj, yj, zj;
             pos.load(j, xj, yj, zj);
             const double dv[3] = {xj - xi, yj - yi, zj - zi};
-            const double l2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+            const double l2 = len2(dv[0], dv[1], dv[2]);
             const double s = c.k * (l2 - c.L2) * rsqrt(l2);
             gx += s * dv[0]; gy += s * dv[1]; gz += s * dv[2];
             const double hs = 0.5 * s;
