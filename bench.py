@@ -9,8 +9,10 @@ the stress read back to the host.
 
 Metric: fiber-element updates/s = sum_p fibers_p * passes_p / wall time.
 Beside it: the same networks' per-problem launch loop (a sample solved to
-convergence) and the CPU oracle (a bounded sample, all host threads).
-Prints one JSON line.
+convergence), the FP32-state solve of the batch with its per-network stress
+error, the continuous-batching serving loop over the batch as a resident
+pool (p50/p99 latency at three offered rates), and the CPU oracle (a bounded
+sample, all host threads).  Prints one JSON line.
 """
 import argparse
 import json
@@ -67,6 +69,74 @@ def cpu_baseline(batch, beta, tol, target_s=15.0):
                       f"(fixed pass count), one network per thread, {wall:.1f}s wall"}
 
 
+def fp32_leg(batch, beta, r64, M, stream):
+    """The same batch with FP32 nodal state and force gather (FP64 norms and
+    stress), tol 1e-6 with a 50 000-pass stall guard; stress error per network
+    against this FP64 solve (itself within 1e-7 of the FP64 oracle)."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07030_amd import dr
+    b = dr.DRBatch(batch, tol=1e-6, damping=beta, dt_safety=0.9, precision=dr.DR_FP32,
+                   stall_window=50_000, stream=stream.cuda_stream)
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    b.solve_device(Fd)
+    b.results()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.solve_device(Fd)
+    r = b.results()
+    wall = time.perf_counter() - t
+    s32 = r["sigma"].reshape(len(batch), 9)
+    s64 = r64["sigma"].reshape(len(batch), 9)
+    err = np.linalg.norm(s32 - s64, axis=1) / np.linalg.norm(s64, axis=1)
+    upd = float((M * r["iters"]).sum())
+    b.close()
+    return {"value": upd / wall, "unit": "fiber-updates/s", "wall_s": wall,
+            "converged": int((r["result"] == dr.DR_CONVERGED).sum()),
+            "stalled": int((r["result"] == dr.DR_STALLED).sum()),
+            "rho_median": float(np.median(r["rho"])), "rho_max": float(r["rho"].max()),
+            "passes_median": int(np.median(r["iters"])), "passes_max": int(r["iters"].max()),
+            "sigma_rel_err_vs_fp64": {"median": float(np.median(err)),
+                                      "p99": float(np.percentile(err, 99)),
+                                      "max": float(err.max())},
+            "per_network_sigma_rel_err": [float(x) for x in err]}
+
+
+def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
+    """Continuous batching over the resident batch as the pool (FP64): a
+    closed-loop run gives the saturated solve rate; open-loop Poisson arrivals
+    at 0.5, 0.8 and 0.95 of it give p50/p99 latency and throughput."""
+    import numpy as np
+
+    from paper_2305_07030_amd import serve as SV
+    dev = SV.PoolDevice(batch, tol=1e-8, damping=beta, dt_safety=0.9)
+    budget = SV.STATE_BYTES_PER_NODE * int(sum(n.n_nodes for n in batch.nets))
+
+    def mk():
+        return SV.Server(dev, hbm_budget_bytes=budget, max_slots=len(batch), tick_passes=4000)
+    F0 = batch.F.copy()
+    # warm the pool: every network solved once, so requests start warm
+    warm = mk()
+    for p in range(len(batch)):
+        warm.submit(SV.Request(-1 - p, p, F0[p], 0.0))
+    while not warm.idle():
+        warm.tick()
+    closed = SV.run_closed_loop(mk(), SV.RequestStream(F0, 0.0, 0.002, seed=50), n_closed)
+    sat = closed.summary()["throughput_per_s"]
+    out = {"pool": f"{len(batch)} networks (N ~ U{{1000..5000}}), FP64, tol 1e-8, warm starts, "
+                   f"F <- F + sym U(+-0.002) per request, tick = 4000 passes",
+           "saturated_solves_per_s": sat, "closed_loop": closed.summary(), "rates": []}
+    for frac in (0.5, 0.8, 0.95):
+        st = SV.run_open_loop(mk(), SV.RequestStream(F0, frac * sat, 0.002, seed=51), n_warm,
+                              n_meas, max_wall=120.0)
+        d = st.summary()
+        d["offered_per_s"] = frac * sat
+        out["rates"].append(d)
+    dev.b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +147,8 @@ def main():
     ap.add_argument("--placement", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -177,6 +249,12 @@ def main():
                                 "speedup_batched_over_loop": value / (lupd / lw)}
         lb.close()
         log("loop baseline:", out["loop_baseline"])
+    if not args.no_fp32 and args.workload == "uniform":
+        out["fp32"] = fp32_leg(batch, beta, r, M, stream)
+        log("fp32:", {k: v for k, v in out["fp32"].items() if k != "per_network_sigma_rel_err"})
+    if not args.no_serve and args.workload == "uniform":
+        out["serving"] = serving_leg(batch, beta)
+        log("serving:", out["serving"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(batch, beta, tol)
         log("cpu baseline:", out["cpu_baseline"])

@@ -65,7 +65,10 @@ typedef enum {
 typedef enum {
     DR_CONVERGED = 0, /* rho <= tol */
     DR_MAX_ITER = 1,  /* max_iter passes made without reaching tol */
-    DR_NONFINITE = 2  /* a residual or energy became NaN / Inf */
+    DR_NONFINITE = 2, /* a residual or energy became NaN / Inf */
+    DR_RUNNING = 3,   /* started by dr_advance and not finished yet */
+    DR_IDLE = 4,      /* no solve has been started for this problem */
+    DR_STALLED = 5    /* rho made no 0.1 % progress for stall_window passes */
 } dr_result;
 
 typedef enum { DR_FP64 = 0, DR_FP32 = 1 } dr_precision;
@@ -77,6 +80,7 @@ typedef enum {
 } dr_placement;
 
 typedef enum {
+    DR_RESUME = -1,      /* dr_advance only: continue the problem's running solve */
     DR_START_AFFINE = 0, /* free nodes start at (F - I) X (cold start) */
     DR_START_ZERO = 1,   /* free nodes start at u = 0 (Fig. 1, commented init) */
     DR_START_WARM = 2    /* u_prev + (F - F_prev) X from the problem's last solve */
@@ -118,6 +122,14 @@ typedef struct {
  *   placement   a dr_placement value; DR_PLACE_LDS is rejected at creation
  *               when the largest problem does not fit (3 * 8 B per node of
  *               LDS, at most 8 nodes per thread)
+ *   chunk       incidences whose loads the force gather issues together:
+ *               0 = automatic, else 2 or 4 (a tuning knob; results do not
+ *               depend on it)
+ *   stall_window  >= 0; 0 = off.  Otherwise a solve also ends (DR_STALLED)
+ *               when its best residual has not improved by 0.1 % during the
+ *               last stall_window passes.  Not part of the paper's loop: a
+ *               guard for the FP32 state, whose force rounding puts a floor
+ *               under the reachable residual.
  */
 typedef struct {
     int32_t precision;
@@ -127,10 +139,13 @@ typedef struct {
     double dt_safety;
     int32_t block;
     int32_t placement;
+    int32_t chunk;
+    int64_t stall_window;
 } dr_options;
 
 /* Fills *opt with the defaults: FP64, tol 1e-8, max_iter 2000000,
- * damping 1e-3, dt_safety 0.9, block 0, placement DR_PLACE_AUTO. */
+ * damping 1e-3, dt_safety 0.9, block 0, placement DR_PLACE_AUTO, chunk 0,
+ * stall_window 0. */
 void dr_options_default(dr_options *opt);
 
 /*
@@ -161,22 +176,22 @@ dr_status dr_solve(dr_batch *b, const double *F, const int32_t *ids,
                    int32_t n_ids, int32_t start);
 
 /*
- * As dr_solve, with F_device [n_ids * 9] and ids_device [n_ids] already in
- * device memory (ids_device may be NULL for all problems in order).  The
- * arrays must stay valid until the solve has finished on the stream.  No
- * host-device copy is enqueued; the ids are not validated on the host.
+ * As dr_solve, with F_device [n_ids * 9] already in device memory; ids is a
+ * host array as in dr_solve (NULL = all problems in order).  F_device must
+ * stay valid until the solve has finished on the stream; F is not checked on
+ * the host (a non-finite F ends that problem with DR_NONFINITE).
  */
-dr_status dr_solve_device(dr_batch *b, const double *F_device,
-                          const int32_t *ids_device, int32_t n_ids, int32_t start);
+dr_status dr_solve_device(dr_batch *b, const double *F_device, const int32_t *ids,
+                          int32_t n_ids, int32_t start);
 
 /*
- * Waits for the last solve and returns its results, in the order of that
- * solve's ids.  Any output pointer may be NULL.
+ * Waits for the last dr_solve / dr_solve_device / dr_solve_loop / dr_advance
+ * and returns its results in the order of that call's ids.  Any output may
+ * be NULL.
  *   sigma      [n_ids * 9]  boundary (reaction) form of the Cauchy stress
  *   sigma_fib  [n_ids * 9]  fiber (virial) form
- *   u          [total_nodes * 3] displacements of ALL problems of the batch,
- *              caller node order, xyz interleaved (the problems not in the
- *              last solve keep their previous state)
+ *   u          [total_nodes * 3] displacements of ALL problems of the batch
+ *              (each problem's last finished solve), caller node order
  *   result     [n_ids] dr_result
  *   iters      [n_ids] DR passes made
  *   resid      [n_ids] final rho
@@ -186,6 +201,36 @@ dr_status dr_solve_device(dr_batch *b, const double *F_device,
 dr_status dr_stress(dr_batch *b, double *sigma, double *sigma_fib, double *u,
                     int32_t *result, int64_t *iters, double *resid, double *ke);
 
+/*
+ * Iteration-level continuous batching: one launch that advances every listed
+ * problem by at most `budget` DR passes, asynchronously.  Slot k works on
+ * problem ids[k]:
+ *   starts[k] a dr_start value  -> a new solve with F + 9 k (host array);
+ *   starts[k] == DR_RESUME      -> continues the problem's running solve from
+ *                                  the state saved in HBM (F + 9 k ignored).
+ * A solve that reaches tol, max_iter or a non-finite value finishes inside the
+ * launch (displacements, scalars and stress are then final); one that spends
+ * the budget saves its exact state, so a solve split over several launches
+ * gives the same bits as one dr_solve.  A problem's arithmetic does not
+ * depend on the other slots of the launch.
+ * Errors: DR_E_INVALID (ids out of range or repeated, DR_RESUME for a problem
+ * that is not running, budget < 1, F of a new solve not finite or det <= 0),
+ * DR_E_DEVICE.
+ */
+dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                     int32_t n_ids, int64_t budget);
+
+/*
+ * Waits for the batch's stream and returns the current results of the
+ * listed problems (host array ids [n_ids]); any output may be NULL.  result
+ * is DR_RUNNING for a solve still in progress (iters / resid / ke then
+ * describe its last pass and sigma is not yet valid) and DR_IDLE for a
+ * problem never solved.  Same layouts as dr_stress.
+ */
+dr_status dr_results(dr_batch *b, const int32_t *ids, int32_t n_ids, double *sigma,
+                     double *sigma_fib, int32_t *result, int64_t *iters, double *resid,
+                     double *ke);
+
 /* Blocks until all work enqueued on the batch's stream has finished. */
 dr_status dr_sync(dr_batch *b);
 
@@ -194,7 +239,8 @@ dr_status dr_sync(dr_batch *b);
  * iteration as dr_solve, run for one problem at a time with a few kernel
  * launches per DR pass and the residual read back and tested on the host
  * after every pass.  Comparator only; same arguments and results as
- * dr_solve followed by dr_stress for the given ids, and synchronous.
+ * dr_solve followed by dr_stress for the given ids, and synchronous.  FP64
+ * batches only (DR_E_INVALID for a DR_FP32 batch).
  */
 dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids,
                         int32_t n_ids, int32_t start);

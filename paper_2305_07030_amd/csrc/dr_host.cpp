@@ -22,6 +22,7 @@
 #include "dr_layout.h"
 
 using drk::KL;
+using drk::KL32;
 using drk::LaunchPlan;
 using drk::ProbDesc;
 using drk::SolveArgs;
@@ -59,11 +60,6 @@ struct HostProblem {
     std::vector<int32_t> new_of_old;
 };
 
-template <class T> struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
-};
-
 } // namespace
 
 struct dr_batch {
@@ -75,47 +71,53 @@ struct dr_batch {
     int32_t n_max = 0;
     std::vector<HostProblem> hp;
     std::vector<ProbDesc> desc;
-    // device arrays
+    // device arrays: network
     ProbDesc *d_probs = nullptr;
     double *d_X = nullptr, *d_invm = nullptr, *d_mass = nullptr;
+    float *d_invm32 = nullptr, *d_mass32 = nullptr;
     int32_t *d_deg = nullptr, *d_slice_w = nullptr, *d_nbr = nullptr;
     int64_t *d_slice_off = nullptr;
     KL *d_kl = nullptr;
-    double *d_u = nullptr, *d_F_last = nullptr;
-    int32_t *d_has_state = nullptr;
-    double *d_xg = nullptr, *d_wg = nullptr;
-    // per-solve
-    double *d_F = nullptr;
-    int32_t *d_ids = nullptr, *d_order = nullptr;
+    KL32 *d_kl32 = nullptr;
+    // device arrays: state and results (per problem)
+    double *d_u = nullptr, *d_qbuf = nullptr, *d_wbuf = nullptr;
+    double *d_F_cur = nullptr, *d_F_last = nullptr;
+    int32_t *d_has_state = nullptr, *d_status = nullptr;
     double *d_sigma = nullptr, *d_sigma_fib = nullptr, *d_rho = nullptr, *d_ke = nullptr;
-    int64_t *d_iters = nullptr;
-    int32_t *d_status = nullptr;
+    int64_t *d_iters = nullptr, *d_n_best = nullptr;
+    double *d_rho_best = nullptr;
+    // device arrays: per launch slot
+    double *d_F = nullptr;
+    int32_t *d_ids = nullptr, *d_order = nullptr, *d_starts = nullptr;
     double *d_partial = nullptr, *d_scalars = nullptr;
     // pinned staging
     double *h_F = nullptr;
-    int32_t *h_ids = nullptr, *h_order = nullptr;
+    int32_t *h_ids = nullptr, *h_order = nullptr, *h_starts = nullptr;
     double *h_scalars = nullptr;
     hipEvent_t staged = nullptr;
-    // last solve
+    // host mirror of which problems have a running solve (for DR_RESUME checks)
+    std::vector<char> running;
+    // last dr_solve* call
     int32_t last_n = -1;
     std::vector<int32_t> last_ids;
-    // One launch shape for every solve of the batch (fixed at creation from
+    // One launch shape for every launch of the batch (fixed at creation from
     // the largest problem), so a problem's arithmetic -- and its result, bit
     // for bit -- does not depend on which other problems share the launch.
-    LaunchPlan plan{0, 0, 0};
+    LaunchPlan plan{0, 0, 0, 4, 0};
 };
 
 namespace {
 
 void free_all(dr_batch *b)
 {
-    void *dev[] = {b->d_probs, b->d_X, b->d_invm, b->d_mass, b->d_deg, b->d_slice_w, b->d_nbr,
-                   b->d_slice_off, b->d_kl, b->d_u, b->d_F_last, b->d_has_state, b->d_xg,
-                   b->d_wg, b->d_F, b->d_ids, b->d_order, b->d_sigma, b->d_sigma_fib, b->d_rho,
-                   b->d_ke, b->d_iters, b->d_status, b->d_partial, b->d_scalars};
+    void *dev[] = {b->d_probs, b->d_X, b->d_invm, b->d_mass, b->d_invm32, b->d_mass32, b->d_deg,
+                   b->d_slice_w, b->d_nbr, b->d_slice_off, b->d_kl, b->d_kl32, b->d_u, b->d_qbuf,
+                   b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
+                   b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
+                   b->d_starts, b->d_partial, b->d_scalars};
     for (void *p : dev)
         if (p) (void)hipFree(p);
-    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_scalars};
+    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     if (b->staged) (void)hipEventDestroy(b->staged);
@@ -141,8 +143,6 @@ dr_status validate_options(const dr_options *o)
     if (!o) return fail(DR_E_INVALID, "options is NULL");
     if (o->precision != DR_FP64 && o->precision != DR_FP32)
         return fail(DR_E_INVALID, "precision %d is not DR_FP64 or DR_FP32", o->precision);
-    if (o->precision == DR_FP32)
-        return fail(DR_E_INVALID, "precision DR_FP32 is not available in this build");
     if (!(o->tol > 0.0) || !std::isfinite(o->tol))
         return fail(DR_E_INVALID, "tol must be finite and > 0 (got %g)", o->tol);
     if (o->max_iter < 1) return fail(DR_E_INVALID, "max_iter must be >= 1");
@@ -154,6 +154,9 @@ dr_status validate_options(const dr_options *o)
         return fail(DR_E_INVALID, "block must be 0, 256, 512 or 1024 (got %d)", o->block);
     if (o->placement < DR_PLACE_AUTO || o->placement > DR_PLACE_GLOBAL)
         return fail(DR_E_INVALID, "placement %d is not a dr_placement value", o->placement);
+    if (o->chunk != 0 && o->chunk != 2 && o->chunk != 4)
+        return fail(DR_E_INVALID, "chunk must be 0, 2 or 4 (got %d)", o->chunk);
+    if (o->stall_window < 0) return fail(DR_E_INVALID, "stall_window must be >= 0");
     return DR_OK;
 }
 
@@ -162,9 +165,11 @@ struct Packed {
     std::vector<ProbDesc> desc;
     std::vector<HostProblem> hp;
     std::vector<double> X, invm, mass;
+    std::vector<float> invm32, mass32;
     std::vector<int32_t> deg, slice_w, nbr;
     std::vector<int64_t> slice_off;
     std::vector<KL> kl;
+    std::vector<KL32> kl32;
     int32_t n_max = 0;
 };
 
@@ -175,6 +180,7 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
     if (P < 1) return fail(DR_E_INVALID, "n_problems must be >= 1 (got %d)", P);
     if (!nets->node_offsets || !nets->fiber_offsets || !nets->X || !nets->EA || !nets->fixed)
         return fail(DR_E_INVALID, "a required network array is NULL");
+    const bool fp32 = opt->precision == DR_FP32;
     const int64_t *no = nets->node_offsets, *fo = nets->fiber_offsets;
     if (no[0] != 0 || fo[0] != 0) return fail(DR_E_INVALID, "offsets must start at 0");
     for (int32_t p = 0; p < P; ++p) {
@@ -198,6 +204,10 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
     pk.invm.resize(total_nodes);
     pk.mass.resize(total_nodes);
     pk.deg.resize(total_nodes);
+    if (fp32) {
+        pk.invm32.resize(total_nodes);
+        pk.mass32.resize(total_nodes);
+    }
 
     for (int32_t p = 0; p < P; ++p) {
         const int32_t N = (int32_t)(no[p + 1] - no[p]);
@@ -305,6 +315,10 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
             pk.mass[node_base + r] = m[i];
             pk.invm[node_base + r] = 1.0 / m[i];
             pk.deg[node_base + r] = degree[i];
+            if (fp32) {
+                pk.mass32[node_base + r] = (float)m[i];
+                pk.invm32[node_base + r] = (float)(1.0 / m[i]);
+            }
         }
         if (N > pk.n_max) pk.n_max = N;
         // sliced ELL incidences
@@ -320,6 +334,7 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
             const size_t base = pk.nbr.size();
             pk.nbr.resize(base + (size_t)width * drk::kWave, 0);
             pk.kl.resize(base + (size_t)width * drk::kWave, KL{0.0, 0.0});
+            if (fp32) pk.kl32.resize(base + (size_t)width * drk::kWave, KL32{0.f, 0.f, 0.f, 0.f});
             for (int32_t lane = 0; lane < drk::kWave; ++lane) {
                 const int32_t r = q * drk::kWave + lane;
                 if (r >= N) continue;
@@ -329,7 +344,12 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
                     const int32_t other = fib[2 * f] == i ? fib[2 * f + 1] : fib[2 * f];
                     const size_t e = base + (size_t)k * drk::kWave + lane;
                     pk.nbr[e] = h.new_of_old[other];
-                    pk.kl[e] = KL{EA[f] / (2.0 * L2[f]), L2[f]};
+                    const double kf = EA[f] / (2.0 * L2[f]);
+                    pk.kl[e] = KL{kf, L2[f]};
+                    if (fp32)
+                        pk.kl32[e] = KL32{(float)(X[3 * other] - X[3 * i]),
+                                          (float)(X[3 * other + 1] - X[3 * i + 1]),
+                                          (float)(X[3 * other + 2] - X[3 * i + 2]), (float)kf};
                 }
             }
             off += (int64_t)width * drk::kWave;
@@ -369,49 +389,61 @@ dr_status create_device(dr_batch *b, Packed &pk)
     UP(d_X, X)
     UP(d_invm, invm)
     UP(d_mass, mass)
+    UP(d_invm32, invm32)
+    UP(d_mass32, mass32)
     UP(d_deg, deg)
     UP(d_slice_w, slice_w)
     UP(d_slice_off, slice_off)
     UP(d_nbr, nbr)
     UP(d_kl, kl)
+    UP(d_kl32, kl32)
 #undef UP
     const size_t P = (size_t)b->P, nodes = (size_t)b->total_nodes;
 #define ZS(dst, n)                                                                                \
     if ((s = dev_zeros(&b->dst, (n), st)) != DR_OK) return s;
     ZS(d_u, 3 * nodes)
+    ZS(d_qbuf, 4 * nodes)
+    ZS(d_wbuf, 4 * nodes)
+    ZS(d_F_cur, 9 * P)
     ZS(d_F_last, 9 * P)
     ZS(d_has_state, P)
-    ZS(d_xg, 4 * nodes)
-    ZS(d_wg, 4 * nodes)
-    ZS(d_F, 9 * P)
-    ZS(d_ids, P)
-    ZS(d_order, P)
+    ZS(d_status, P)
     ZS(d_sigma, 9 * P)
     ZS(d_sigma_fib, 9 * P)
     ZS(d_rho, P)
     ZS(d_ke, P)
     ZS(d_iters, P)
-    ZS(d_status, P)
+    ZS(d_n_best, P)
+    ZS(d_rho_best, P)
+    ZS(d_F, 9 * P)
+    ZS(d_ids, P)
+    ZS(d_order, P)
+    ZS(d_starts, P)
     ZS(d_partial, 3 * ((size_t)pk.n_max / 256 + 2))
     ZS(d_scalars, 8)
 #undef ZS
+    const int rc = drk::launch_fill_i32(b->d_status, DR_IDLE, (int64_t)P, st);
+    if (rc != 0) return fail(DR_E_DEVICE, "status fill failed: %s", drk::kernel_error_string(rc));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_F), 9 * P * sizeof(double), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_ids), P * sizeof(int32_t), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_order), P * sizeof(int32_t), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_starts), P * sizeof(int32_t), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_scalars), 8 * sizeof(double), 0));
     HIPCHECK(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
     HIPCHECK(hipStreamSynchronize(st));
     return DR_OK;
 }
 
-// Launch shape for a solve whose largest problem has n_max nodes.  Returns
+// Launch shape for a batch whose largest problem has n_max nodes.  Returns
 // npt = -1 when DR_PLACE_LDS was asked for and the problem does not fit.
 LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
 {
     LaunchPlan pl{};
+    pl.fp32 = opt.precision == DR_FP32;
+    const int elem = pl.fp32 ? 4 : 8; // bytes per state value in LDS
     const int block = opt.block;
-    auto reg_lds = [](int blk, int n) { return ((blk / drk::kWave) * 20 + 3 * n) * 8; };
-    // register-resident variant when the positions fit in LDS
+    auto reg_lds = [&](int blk, int n) { return (blk / drk::kWave) * 20 * 8 + 3 * n * elem; };
+    // register-resident variant when the state fits in LDS
     int blk = block;
     if (blk == 0) blk = n_max > 2048 ? 1024 : (n_max > 256 ? 512 : 256);
     int npt = (n_max + blk - 1) / blk;
@@ -426,6 +458,8 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
         return pl;
     }
     if (fits && opt.placement != DR_PLACE_GLOBAL) {
+        // chunks of 2 keep the 1024-thread FP64 variants within 128 VGPRs
+        pl.chunk = opt.chunk ? opt.chunk : ((blk == 1024 && !pl.fp32) ? 2 : 4);
         pl.block = blk;
         pl.npt = npt < 1 ? 1 : npt;
         pl.lds_bytes = reg_lds(blk, n_max);
@@ -433,50 +467,66 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     }
     pl.block = block ? block : 1024;
     pl.npt = 0;
+    pl.chunk = 4;
     pl.lds_bytes = (pl.block / drk::kWave) * 20 * 8;
     return pl;
 }
 
-SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, bool with_ids, bool with_order)
+SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
 {
     SolveArgs a{};
     a.probs = b->d_probs;
-    a.ids = with_ids ? b->d_ids : nullptr;
-    a.order = with_order ? b->d_order : nullptr;
+    a.ids = b->d_ids;
+    a.order = b->d_order;
+    a.starts = nullptr;
     a.F = b->d_F;
     a.n_solve = n_solve;
     a.start = start;
     a.tol = b->opt.tol;
     a.max_iter = b->opt.max_iter;
+    a.budget = budget;
     a.X = b->d_X;
     a.invm = b->d_invm;
     a.mass = b->d_mass;
+    a.invm32 = b->d_invm32;
+    a.mass32 = b->d_mass32;
     a.deg = b->d_deg;
     a.slice_w = b->d_slice_w;
     a.slice_off = b->d_slice_off;
     a.nbr = b->d_nbr;
     a.kl = b->d_kl;
+    a.kl32 = b->d_kl32;
     a.u = b->d_u;
+    a.qbuf = b->d_qbuf;
+    a.wbuf = b->d_wbuf;
+    a.F_cur = b->d_F_cur;
     a.F_last = b->d_F_last;
     a.has_state = b->d_has_state;
-    a.xg = b->d_xg;
-    a.wg = b->d_wg;
     a.sigma = b->d_sigma;
     a.sigma_fib = b->d_sigma_fib;
     a.iters = b->d_iters;
+    a.rho_best = b->d_rho_best;
+    a.n_best = b->d_n_best;
+    a.stall_window = b->opt.stall_window;
     a.rho = b->d_rho;
     a.ke = b->d_ke;
     a.status = b->d_status;
     return a;
 }
 
-dr_status check_solve_args(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
-                           int32_t start)
+dr_status check_F(const double *F, int32_t k)
 {
-    if (!b) return fail(DR_E_INVALID, "batch is NULL");
-    if (!F) return fail(DR_E_INVALID, "F is NULL");
-    if (start < DR_START_AFFINE || start > DR_START_WARM)
-        return fail(DR_E_INVALID, "start mode %d is not a dr_start value", start);
+    const double *f = F + 9 * (int64_t)k;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(f[i])) return fail(DR_E_INVALID, "F of slot %d is not finite", k);
+    const double J = f[0] * (f[4] * f[8] - f[5] * f[7]) - f[1] * (f[3] * f[8] - f[5] * f[6]) +
+                     f[2] * (f[3] * f[7] - f[4] * f[6]);
+    if (!(J > 0.0)) return fail(DR_E_INVALID, "det F of slot %d is not > 0 (%g)", k, J);
+    return DR_OK;
+}
+
+dr_status check_ids(dr_batch *b, const int32_t *ids, int32_t n_ids)
+{
     if (n_ids < 1 || n_ids > b->P)
         return fail(DR_E_INVALID, "n_ids must be in [1, %d] (got %d)", b->P, n_ids);
     if (!ids && n_ids != b->P)
@@ -490,38 +540,82 @@ dr_status check_solve_args(dr_batch *b, const double *F, const int32_t *ids, int
             seen[ids[k]] = 1;
         }
     }
-    for (int64_t k = 0; k < 9LL * n_ids; ++k)
-        if (!std::isfinite(F[k])) return fail(DR_E_INVALID, "F[%lld] is not finite", (long long)k);
-    for (int32_t k = 0; k < n_ids; ++k) {
-        const double *f = F + 9 * (int64_t)k;
-        const double J = f[0] * (f[4] * f[8] - f[5] * f[7]) - f[1] * (f[3] * f[8] - f[5] * f[6]) +
-                         f[2] * (f[3] * f[7] - f[4] * f[6]);
-        if (!(J > 0.0)) return fail(DR_E_INVALID, "det F of solve %d is not > 0 (%g)", k, J);
-    }
     return DR_OK;
 }
 
-// Stages F and ids, sorts the slots largest-first and uploads them.
-dr_status stage_solve(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids)
+dr_status check_start(int32_t start, bool allow_resume)
+{
+    if (start < (allow_resume ? DR_RESUME : DR_START_AFFINE) || start > DR_START_WARM)
+        return fail(DR_E_INVALID, "start mode %d is not valid here", start);
+    return DR_OK;
+}
+
+// Stages F (may be NULL), ids, starts (may be NULL) and the largest-first
+// slot order, and uploads them.
+dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                int32_t n_ids)
 {
     HIPCHECK(hipEventSynchronize(b->staged)); // previous staging consumed
-    std::memcpy(b->h_F, F, 9 * sizeof(double) * (size_t)n_ids);
+    if (F) std::memcpy(b->h_F, F, 9 * sizeof(double) * (size_t)n_ids);
     b->last_ids.resize(n_ids);
     for (int32_t k = 0; k < n_ids; ++k) {
         b->h_ids[k] = ids ? ids[k] : k;
         b->last_ids[k] = b->h_ids[k];
         b->h_order[k] = k;
+        if (starts) b->h_starts[k] = starts[k];
     }
     std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
         return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
     });
-    HIPCHECK(hipMemcpyAsync(b->d_F, b->h_F, 9 * sizeof(double) * (size_t)n_ids,
-                            hipMemcpyHostToDevice, b->stream));
+    if (F)
+        HIPCHECK(hipMemcpyAsync(b->d_F, b->h_F, 9 * sizeof(double) * (size_t)n_ids,
+                                hipMemcpyHostToDevice, b->stream));
     HIPCHECK(hipMemcpyAsync(b->d_ids, b->h_ids, sizeof(int32_t) * (size_t)n_ids,
                             hipMemcpyHostToDevice, b->stream));
     HIPCHECK(hipMemcpyAsync(b->d_order, b->h_order, sizeof(int32_t) * (size_t)n_ids,
                             hipMemcpyHostToDevice, b->stream));
+    if (starts)
+        HIPCHECK(hipMemcpyAsync(b->d_starts, b->h_starts, sizeof(int32_t) * (size_t)n_ids,
+                                hipMemcpyHostToDevice, b->stream));
     HIPCHECK(hipEventRecord(b->staged, b->stream));
+    return DR_OK;
+}
+
+// Copies per-problem results for `ids` to the host (waits for the stream).
+dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sigma,
+                         double *sigma_fib, int32_t *result, int64_t *iters, double *resid,
+                         double *ke)
+{
+    const size_t P = (size_t)b->P;
+    std::vector<double> sg, sf, rh, kk;
+    std::vector<int32_t> stt(P);
+    std::vector<int64_t> it;
+    hipStream_t st = b->stream;
+    if (sigma) { sg.resize(9 * P); HIPCHECK(hipMemcpyAsync(sg.data(), b->d_sigma, 9 * P * 8, hipMemcpyDeviceToHost, st)); }
+    if (sigma_fib) { sf.resize(9 * P); HIPCHECK(hipMemcpyAsync(sf.data(), b->d_sigma_fib, 9 * P * 8, hipMemcpyDeviceToHost, st)); }
+    HIPCHECK(hipMemcpyAsync(stt.data(), b->d_status, P * 4, hipMemcpyDeviceToHost, st));
+    if (iters) { it.resize(P); HIPCHECK(hipMemcpyAsync(it.data(), b->d_iters, P * 8, hipMemcpyDeviceToHost, st)); }
+    if (resid) { rh.resize(P); HIPCHECK(hipMemcpyAsync(rh.data(), b->d_rho, P * 8, hipMemcpyDeviceToHost, st)); }
+    if (ke) { kk.resize(P); HIPCHECK(hipMemcpyAsync(kk.data(), b->d_ke, P * 8, hipMemcpyDeviceToHost, st)); }
+    HIPCHECK(hipStreamSynchronize(st));
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t p = ids[k];
+        if (sigma) std::memcpy(sigma + 9 * (size_t)k, sg.data() + 9 * (size_t)p, 72);
+        if (sigma_fib) std::memcpy(sigma_fib + 9 * (size_t)k, sf.data() + 9 * (size_t)p, 72);
+        if (result) result[k] = stt[p];
+        if (iters) iters[k] = it[p];
+        if (resid) resid[k] = rh[p];
+        if (ke) ke[k] = kk[p];
+    }
+    // the stream is idle: refresh the host mirror of running solves
+    for (size_t p = 0; p < P; ++p) b->running[p] = stt[p] == DR_RUNNING;
+    return DR_OK;
+}
+
+dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
+{
+    const int rc = drk::launch_solve(a, b->plan, b->stream);
+    if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
     return DR_OK;
 }
 
@@ -539,6 +633,8 @@ void dr_options_default(dr_options *o)
     o->dt_safety = 0.9;
     o->block = 0;
     o->placement = DR_PLACE_AUTO;
+    o->chunk = 0;
+    o->stall_window = 0;
 }
 
 const char *dr_last_error(void) { return g_err.c_str(); }
@@ -570,6 +666,7 @@ dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt, void *
         b->n_max = pk.n_max;
         b->plan = plan_for(*opt, pk.n_max);
         b->desc = pk.desc;
+        b->running.assign(b->P, 0);
         s = create_device(b, pk);
         if (s != DR_OK) {
             free_all(b);
@@ -590,13 +687,16 @@ dr_status dr_solve(dr_batch *b, const double *F, const int32_t *ids, int32_t n_i
 {
     try {
         g_err.clear();
-        dr_status s = check_solve_args(b, F, ids, n_ids, start);
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!F) return fail(DR_E_INVALID, "F is NULL");
+        dr_status s = check_start(start, false);
         if (s != DR_OK) return s;
-        s = stage_solve(b, F, ids, n_ids);
-        if (s != DR_OK) return s;
-        const SolveArgs a = make_args(b, n_ids, start, true, true);
-        const int rc = drk::launch_solve(a, b->plan, b->stream);
-        if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+        if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
+        for (int32_t k = 0; k < n_ids; ++k)
+            if ((s = check_F(F, k)) != DR_OK) return s;
+        if ((s = stage(b, F, ids, nullptr, n_ids)) != DR_OK) return s;
+        if ((s = launch_or_fail(b, make_args(b, n_ids, start, b->opt.max_iter))) != DR_OK) return s;
+        for (int32_t k = 0; k < n_ids; ++k) b->running[b->h_ids[k]] = 0;
         b->last_n = n_ids;
         return DR_OK;
     } catch (const std::bad_alloc &) {
@@ -606,29 +706,76 @@ dr_status dr_solve(dr_batch *b, const double *F, const int32_t *ids, int32_t n_i
     }
 }
 
-dr_status dr_solve_device(dr_batch *b, const double *F_device, const int32_t *ids_device,
-                          int32_t n_ids, int32_t start)
+dr_status dr_solve_device(dr_batch *b, const double *F_device, const int32_t *ids, int32_t n_ids,
+                          int32_t start)
 {
     try {
         g_err.clear();
         if (!b) return fail(DR_E_INVALID, "batch is NULL");
         if (!F_device) return fail(DR_E_INVALID, "F_device is NULL");
-        if (start < DR_START_AFFINE || start > DR_START_WARM)
-            return fail(DR_E_INVALID, "start mode %d is not a dr_start value", start);
-        if (n_ids < 1 || n_ids > b->P)
-            return fail(DR_E_INVALID, "n_ids must be in [1, %d] (got %d)", b->P, n_ids);
-        if (!ids_device && n_ids != b->P)
-            return fail(DR_E_INVALID, "ids_device is NULL but n_ids != n_problems");
-        SolveArgs a = make_args(b, n_ids, start, false, false);
+        dr_status s = check_start(start, false);
+        if (s != DR_OK) return s;
+        if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
+        if ((s = stage(b, nullptr, ids, nullptr, n_ids)) != DR_OK) return s;
+        SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
         a.F = F_device;
-        a.ids = ids_device;
-        const int rc = drk::launch_solve(a, b->plan, b->stream);
-        if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+        if ((s = launch_or_fail(b, a)) != DR_OK) return s;
+        for (int32_t k = 0; k < n_ids; ++k) b->running[b->h_ids[k]] = 0;
         b->last_n = n_ids;
-        b->last_ids.clear(); // unknown on the host
         return DR_OK;
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_solve_device");
+    }
+}
+
+dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                     int32_t n_ids, int64_t budget)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!F || !ids || !starts) return fail(DR_E_INVALID, "F, ids and starts are required");
+        if (budget < 1) return fail(DR_E_INVALID, "budget must be >= 1");
+        dr_status s = check_ids(b, ids, n_ids);
+        if (s != DR_OK) return s;
+        for (int32_t k = 0; k < n_ids; ++k) {
+            if ((s = check_start(starts[k], true)) != DR_OK) return s;
+            if (starts[k] == DR_RESUME) {
+                if (!b->running[ids[k]])
+                    return fail(DR_E_INVALID, "slot %d resumes problem %d, which is not running", k,
+                                ids[k]);
+            } else if ((s = check_F(F, k)) != DR_OK) {
+                return s;
+            }
+        }
+        if ((s = stage(b, F, ids, starts, n_ids)) != DR_OK) return s;
+        SolveArgs a = make_args(b, n_ids, DR_START_AFFINE, budget);
+        a.starts = b->d_starts;
+        if ((s = launch_or_fail(b, a)) != DR_OK) return s;
+        // Until dr_results reads the device status, every slot may still be running.
+        for (int32_t k = 0; k < n_ids; ++k) b->running[ids[k]] = 1;
+        b->last_n = n_ids;
+        return DR_OK;
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_advance");
+    }
+}
+
+dr_status dr_results(dr_batch *b, const int32_t *ids, int32_t n_ids, double *sigma,
+                     double *sigma_fib, int32_t *result, int64_t *iters, double *resid, double *ke)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!ids && n_ids > 0) return fail(DR_E_INVALID, "ids is NULL");
+        for (int32_t k = 0; k < n_ids; ++k)
+            if (ids[k] < 0 || ids[k] >= b->P)
+                return fail(DR_E_INVALID, "ids[%d] = %d is out of range", k, ids[k]);
+        return gather_results(b, ids, n_ids, sigma, sigma_fib, result, iters, resid, ke);
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_results");
     }
 }
 
@@ -647,22 +794,14 @@ dr_status dr_stress(dr_batch *b, double *sigma, double *sigma_fib, double *u, in
         g_err.clear();
         if (!b) return fail(DR_E_INVALID, "batch is NULL");
         if (b->last_n < 0) return fail(DR_E_STATE, "dr_stress called before any dr_solve");
-        const size_t n = (size_t)b->last_n;
-        hipStream_t st = b->stream;
-        if (sigma) HIPCHECK(hipMemcpyAsync(sigma, b->d_sigma, 9 * n * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (sigma_fib)
-            HIPCHECK(hipMemcpyAsync(sigma_fib, b->d_sigma_fib, 9 * n * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (result) HIPCHECK(hipMemcpyAsync(result, b->d_status, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        if (iters) HIPCHECK(hipMemcpyAsync(iters, b->d_iters, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        if (resid) HIPCHECK(hipMemcpyAsync(resid, b->d_rho, n * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (ke) HIPCHECK(hipMemcpyAsync(ke, b->d_ke, n * sizeof(double), hipMemcpyDeviceToHost, st));
-        std::vector<double> ur;
+        dr_status s = gather_results(b, b->last_ids.data(), b->last_n, sigma, sigma_fib, result,
+                                     iters, resid, ke);
+        if (s != DR_OK) return s;
         if (u) {
-            ur.resize(3 * (size_t)b->total_nodes);
-            HIPCHECK(hipMemcpyAsync(ur.data(), b->d_u, ur.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        }
-        HIPCHECK(hipStreamSynchronize(st));
-        if (u) {
+            std::vector<double> ur(3 * (size_t)b->total_nodes);
+            HIPCHECK(hipMemcpyAsync(ur.data(), b->d_u, ur.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, b->stream));
+            HIPCHECK(hipStreamSynchronize(b->stream));
             for (int32_t p = 0; p < b->P; ++p) {
                 const HostProblem &h = b->hp[p];
                 const int64_t nb = b->desc[p].node_base;
@@ -688,23 +827,30 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
 {
     try {
         g_err.clear();
-        dr_status s = check_solve_args(b, F, ids, n_ids, start);
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!F) return fail(DR_E_INVALID, "F is NULL");
+        if (b->opt.precision != DR_FP64)
+            return fail(DR_E_INVALID, "the launch-loop comparator is FP64 only");
+        dr_status s = check_start(start, false);
         if (s != DR_OK) return s;
-        s = stage_solve(b, F, ids, n_ids);
-        if (s != DR_OK) return s;
-        const SolveArgs a = make_args(b, n_ids, start, true, false);
+        if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
+        for (int32_t k = 0; k < n_ids; ++k)
+            if ((s = check_F(F, k)) != DR_OK) return s;
+        if ((s = stage(b, F, ids, nullptr, n_ids)) != DR_OK) return s;
+        SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
+        a.order = nullptr;
         hipStream_t st = b->stream;
         for (int32_t slot = 0; slot < n_ids; ++slot) {
             const ProbDesc &d = b->desc[b->h_ids[slot]];
-            int rc = drk::launch_loop_iteration_kernels(a, slot, 0, d.N, b->d_partial, b->d_scalars,
-                                                        0, st);
+            int rc = drk::launch_loop_kernels(a, slot, 0, d.N, b->d_partial, b->d_scalars, 0, 0.0,
+                                              0.0, 0, st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop set-up launch failed: %s", drk::kernel_error_string(rc));
             int64_t n = 0;
             double rho = 0.0, ke = 0.0;
             int status = DR_MAX_ITER;
             for (;;) {
-                rc = drk::launch_loop_iteration_kernels(a, slot, 1, d.N, b->d_partial, b->d_scalars,
-                                                        n, st);
+                rc = drk::launch_loop_kernels(a, slot, 1, d.N, b->d_partial, b->d_scalars, n, 0.0,
+                                              0.0, 0, st);
                 if (rc != 0) return fail(DR_E_DEVICE, "loop pass launch failed: %s", drk::kernel_error_string(rc));
                 HIPCHECK(hipMemcpyAsync(b->h_scalars, b->d_scalars, 3 * sizeof(double),
                                         hipMemcpyDeviceToHost, st));
@@ -718,9 +864,10 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
                 if (rho <= b->opt.tol) { status = DR_CONVERGED; break; }
                 if (n >= b->opt.max_iter) { status = DR_MAX_ITER; break; }
             }
-            double sc[8] = {0, 0, 0, rho, ke, (double)status, 0, 0};
-            rc = drk::launch_loop_iteration_kernels(a, slot, 2, d.N, b->d_partial, sc, n, st);
+            rc = drk::launch_loop_kernels(a, slot, 2, d.N, b->d_partial, b->d_scalars, n, rho, ke,
+                                          status, st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop stress launch failed: %s", drk::kernel_error_string(rc));
+            b->running[b->h_ids[slot]] = 0;
         }
         HIPCHECK(hipStreamSynchronize(st));
         b->last_n = n_ids;

@@ -1,27 +1,33 @@
 // HIP kernels for batched dynamic relaxation on CDNA4 (gfx950).
 //
-// One workgroup runs the whole dynamic-relaxation loop of Fig. 1 for one
+// One workgroup runs the dynamic-relaxation loop of Fig. 1 for one
 // sub-problem (section III: the loop moved inside a single kernel, one thread
 // team per sub-problem).  Per pass, every thread
-//   1. moves its free nodes: x += dt w            (w = half-step velocity)
+//   1. moves its free nodes: q += dt w            (w = half-step velocity)
 //   2. barrier
 //   3. gathers the internal force on each of its nodes over the node's
 //      incidences (deterministic node -> fiber gather, no atomics)
 //   4. forms the damped acceleration, the full-step and next half-step
-//      velocities, and its share of |g_free|^2, |g_B|^2 and 2 KE
+//      velocities, and its share of |g_free|^2, |g_B|^2 and 2 KE (FP64)
 //   5. wavefront reduction -> LDS -> every thread sums the wave partials in
 //      the same fixed order, so the stop decision is uniform.
-// After the loop the final displacements go to HBM and a separate launch
-// (k_stress) gathers the reactions and both stress forms from them.
+// A launch makes at most `budget` passes per problem.  A solve that is still
+// running when the budget is spent saves its state (exactly) to HBM and a
+// later launch resumes it, so a solve split over several launches gives the
+// same bits as one launch.  A finished solve writes its displacements; a
+// separate launch (k_stress) forms the reactions and both stress forms.
 //
-// Two placements:
-//   k_dr_reg<BLOCK, NPT>: positions in LDS (SoA), the half-step velocity and
-//     degree of each owned node in registers, NPT nodes per thread; for
-//     problems whose positions fit in LDS (3 * 8 B per node).
-//   k_dr_glb<BLOCK>: positions and half-step velocities in device memory,
-//     any problem size.
-// In both, the topology (neighbour id and fiber constants) streams from
-// device memory every pass; it is read-only and stays in L2 / MALL.
+// Placements:
+//   k_dr_reg<P, BLOCK, NPT, CH>: state q in LDS (SoA), the half-step velocity
+//     and degree of each owned node in registers, NPT nodes per thread;
+//   k_dr_glb<P, BLOCK>: state and velocities in device memory, any size.
+// Precision policies:
+//   P64: q = positions x (FP64), fiber constants {EA/(2L^2), L^2};
+//   P32: q = displacement beyond the affine field, u - (F - I) X (FP32),
+//        fiber constants {dX, EA/(2L^2)} in FP32, strain numerator in the
+//        Green form dX.(F^T F - I)dX + 2 (F dX).dq + dq.dq (exactly zero at
+//        the reference state); the norm reductions and the stress are FP64.
+// The topology streams from device memory every pass (L2 / MALL resident).
 #include <hip/hip_runtime.h>
 
 #include "dr_layout.h"
@@ -29,43 +35,105 @@
 namespace drk {
 
 enum { kConverged = 0, kMaxIter = 1, kNonFinite = 2 };
+
+// Progress of a running solve for the optional stall guard.
+struct Progress {
+    double best;  // best residual so far
+    int64_t nbest; // pass at which it was reached
+};
 enum { kStartAffine = 0, kStartZero = 1, kStartWarm = 2 };
 
-// Partial sums kept per wave in LDS: 3 per pass, 18 in the stress epilogue.
+// Partial sums kept per wave in LDS: 3 per pass, 18 in the stress kernel.
 constexpr int kRedStride = 20;
 
+// Cross-lane move of a double with a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Wavefront sum in a fixed order: quad swaps and row rotations (DPP, within
+// rows of 16 lanes), then the two cross-row steps.  Deterministic; lane 0's
+// value is the one the callers use.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
+    v += dpp_f64<0x124>(v); // row_ror:4
+    v += dpp_f64<0x128>(v); // row_ror:8
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
-struct LdsPos {
-    double *xs, *ys, *zs;
-    __device__ __forceinline__ void load(int j, double &x, double &y, double &z) const
+// Squared length, rounded as the host rounds L^2 (no fused multiply-add), so
+// a fiber at its reference length carries exactly zero force.
+__device__ __forceinline__ double len2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+struct P64 {
+    using T = double;
+    static constexpr bool kDisp = false;
+};
+struct P32 {
+    using T = float;
+    static constexpr bool kDisp = true;
+};
+
+// Running state of one problem in LDS, SoA.
+template <class T> struct LdsQ {
+    T *a;
+    int n;
+    __device__ __forceinline__ void load(int j, T &x, T &y, T &z) const
     {
-        x = xs[j]; y = ys[j]; z = zs[j];
+        x = a[j]; y = a[n + j]; z = a[2 * n + j];
     }
-    __device__ __forceinline__ void store(int j, double x, double y, double z) const
+    __device__ __forceinline__ void store(int j, T x, T y, T z) const
     {
-        xs[j] = x; ys[j] = y; zs[j] = z;
+        a[j] = x; a[n + j] = y; a[2 * n + j] = z;
     }
 };
 
-struct GlbPos {
-    double *base; // 4 doubles per node
-    __device__ __forceinline__ void load(int j, double &x, double &y, double &z) const
+// Running state of a node in device memory: a 32-byte record holding the
+// FP64 position (x, y, z, -), or the FP32 state (q0, q1, q2, -) followed by
+// the compensation terms of its summed updates (c0, c1, c2, -).
+template <class T> constexpr int kQStride = sizeof(T) == 8 ? 4 : 8;
+
+template <class T> struct GlbQ {
+    T *base;
+    __device__ __forceinline__ void load(int j, T &x, T &y, T &z) const
     {
-        const double2 a = *reinterpret_cast<const double2 *>(base + 4 * (int64_t)j);
-        x = a.x; y = a.y; z = base[4 * (int64_t)j + 2];
+        const T *q = base + kQStride<T> * (int64_t)j;
+        x = q[0]; y = q[1]; z = q[2];
     }
-    __device__ __forceinline__ void store(int j, double x, double y, double z) const
+    __device__ __forceinline__ void store(int j, T x, T y, T z) const
     {
-        *reinterpret_cast<double2 *>(base + 4 * (int64_t)j) = make_double2(x, y);
-        base[4 * (int64_t)j + 2] = z;
+        T *q = base + kQStride<T> * (int64_t)j;
+        q[0] = x; q[1] = y; q[2] = z;
     }
 };
+
+// q += dt w.  FP64 adds directly.  FP32 uses compensated (Kahan) summation:
+// near convergence dt w falls below half an ulp of q and a plain FP32 add
+// would drop it, freezing the iteration short of equilibrium.
+template <class T>
+__device__ __forceinline__ void advance_q(T &q, T dtw, T &comp)
+{
+    if constexpr (sizeof(T) == 8) {
+        q += dtw;
+    } else {
+        const T y = dtw - comp;
+        const T t = q + y;
+        comp = (t - q) - y;
+        q = t;
+    }
+}
 
 // Slice of node r: first entry (without the lane offset) and width.
 struct Row {
@@ -82,61 +150,45 @@ __device__ __forceinline__ Row node_row(const SolveArgs &A, const ProbDesc &P, i
     return row;
 }
 
-// Squared length, rounded as the host rounds L^2 (no fused multiply-add), so
-// a fiber at its reference length carries exactly zero force.
-__device__ __forceinline__ double len2(double dx, double dy, double dz)
-{
-#pragma clang fp contract(off)
-    return dx * dx + dy * dy + dz * dz;
-}
-
-// Internal force on node r (Fig. 1, getInternalForces): sum over the node's
-// fibers of T d / l with d = x_j - x_i and T = EA (l^2 / L^2 - 1) / 2
+// ---------------------------------------------------------------------------
+// Force gather (Fig. 1, getInternalForces): g_i = sum over the node's fibers
+// of T d / l, d pointing from node i to the neighbour, T = EA (l^2/L^2 - 1)/2
 // = k (l^2 - L^2), k = EA / (2 L^2).
-template <class Pos>
-__device__ __forceinline__ void gather_force(const SolveArgs &A, const Row &row, const Pos &pos,
-                                             int lane, int d, double xi, double yi, double zi,
-                                             double &gx, double &gy, double &gz)
+//
+// The slice width is wave-uniform, so the row is walked in chunks of C
+// incidences whose loads are unconditional: C neighbour ids and constants
+// from L2, then the C neighbour states from LDS, then C independent chains.
+// Entries past the node's own degree (padding up to the slice width) hold a
+// valid neighbour id and are masked out by a select, never by a branch.
+// Contributions are added in ascending incidence order.
+// ---------------------------------------------------------------------------
+template <int C, bool STRESS, class Pos>
+__device__ __forceinline__ void chunk64(const SolveArgs &A, int64_t e, const Pos &pos, int k0,
+                                        int d, double xi, double yi, double zi, double &gx,
+                                        double &gy, double &gz, double *sf)
 {
-    gx = 0.0; gy = 0.0; gz = 0.0;
-    const int64_t e0 = row.e0 + lane;
-    for (int k = 0; k < row.width; ++k) {
-        if (k < d) {
-            const int64_t e = e0 + (int64_t)k * kWave;
-            const int j = A.nbr[e];
-            const KL c = A.kl[e];
-            double xj, yj, zj;
-            pos.load(j, xj, yj, zj);
-            const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-            const double l2 = len2(dx, dy, dz);
-            const double s = c.k * (l2 - c.L2) * rsqrt(l2);
-            gx += s * dx; gy += s * dy; gz += s * dz;
-        }
+    int j[C];
+    KL c[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        j[t] = A.nbr[e + (int64_t)t * kWave];
+        c[t] = A.kl[e + (int64_t)t * kWave];
     }
-}
-
-// Same gather, also accumulating 1/2 (T / l) d (x) d into the fiber stress
-// (each fiber is visited from both ends).
-template <class Pos>
-__device__ __forceinline__ void gather_force_stress(const SolveArgs &A, const Row &row,
-                                                    const Pos &pos, int lane, int d, double xi,
-                                                    double yi, double zi, double &gx, double &gy,
-                                                    double &gz, double *sf)
-{
-    gx = 0.0; gy = 0.0; gz = 0.0;
-    const int64_t e0 = row.e0 + lane;
-    for (int k = 0; k < row.width; ++k) {
-        if (k < d) {
-            const int64_t e = e0 + (int64_t)k * kWave;
-            const int j = A.nbr[e];
-            const KL c = A.kl[e];
-            double xj, yj, zj;
-            pos.load(j, xj, yj, zj);
-            const double dv[3] = {xj - xi, yj - yi, zj - zi};
-            const double l2 = len2(dv[0], dv[1], dv[2]);
-            const double s = c.k * (l2 - c.L2) * rsqrt(l2);
-            gx += s * dv[0]; gy += s * dv[1]; gz += s * dv[2];
+    double dx[C], dy[C], dz[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        pos.load(j[t], dx[t], dy[t], dz[t]);
+        dx[t] -= xi; dy[t] -= yi; dz[t] -= zi;
+    }
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        const double l2 = len2(dx[t], dy[t], dz[t]);
+        double s = c[t].k * (l2 - c[t].L2) * rsqrt(l2);
+        s = (k0 + t < d) ? s : 0.0;
+        gx += s * dx[t]; gy += s * dy[t]; gz += s * dz[t];
+        if (STRESS) {
             const double hs = 0.5 * s;
+            const double dv[3] = {dx[t], dy[t], dz[t]};
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
@@ -145,71 +197,195 @@ __device__ __forceinline__ void gather_force_stress(const SolveArgs &A, const Ro
     }
 }
 
-struct Solve {
-    ProbDesc P;
-    int slot, p;
-    double F[9];
-    double Fl[9];
-    bool warm;
+// FP32 state: q = u - (F - I) X, the displacement beyond the affine field
+// (the smooth affine part would otherwise dominate |u| and round away the
+// small differences between neighbours).  For a fiber with reference vector
+// dX and dq = q_j - q_i:
+//   d = F dX + dq,  l^2 - L^2 = dX.(F^T F - I) dX + 2 (F dX).dq + dq.dq,
+// all of it well conditioned and exactly zero at the reference state.
+struct Aff32 {
+    float F[9]; // row-major F
+    float C[6]; // F^T F - I: C00, C11, C22, 2 C01, 2 C02, 2 C12
 };
 
-__device__ __forceinline__ Solve load_solve(const SolveArgs &A)
+template <int C, class Pos>
+__device__ __forceinline__ void chunk32(const SolveArgs &A, const Aff32 &af, int64_t e,
+                                        const Pos &pos, int k0, int d, float qi0, float qi1,
+                                        float qi2, float &gx, float &gy, float &gz)
 {
-    Solve S;
-    S.slot = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
-    S.p = A.ids ? A.ids[S.slot] : S.slot;
-    S.P = A.probs[S.p];
+    int j[C];
+    KL32 c[C];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) S.F[k] = A.F[9 * (int64_t)S.slot + k];
-    S.warm = (A.start == kStartWarm) && A.has_state[S.p];
+    for (int t = 0; t < C; ++t) {
+        j[t] = A.nbr[e + (int64_t)t * kWave];
+        c[t] = A.kl32[e + (int64_t)t * kWave];
+    }
+    float dq0[C], dq1[C], dq2[C];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) S.Fl[k] = S.warm ? A.F_last[9 * (int64_t)S.p + k] : S.F[k];
-    return S;
-}
-
-// Start position of local node r (Fig. 1 step 4 and the initialisation):
-// prescribed nodes x = F X; free nodes from the affine field, from u = 0, or
-// warm (u_prev + (F - F_prev) X).
-__device__ __forceinline__ void start_position(const SolveArgs &A, const Solve &S, int r,
-                                               double x[3])
-{
-    const int64_t gi = S.P.node_base + r;
-    const double X[3] = {A.X[3 * gi], A.X[3 * gi + 1], A.X[3 * gi + 2]};
-    const bool free_node = r < S.P.N_free;
+    for (int t = 0; t < C; ++t) {
+        pos.load(j[t], dq0[t], dq1[t], dq2[t]);
+        dq0[t] -= qi0; dq1[t] -= qi1; dq2[t] -= qi2;
+    }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double u;
-        const double fx = (S.F[3 * a] - (a == 0 ? 1.0 : 0.0)) * X[0] +
-                          (S.F[3 * a + 1] - (a == 1 ? 1.0 : 0.0)) * X[1] +
-                          (S.F[3 * a + 2] - (a == 2 ? 1.0 : 0.0)) * X[2];
-        if (!free_node || A.start == kStartAffine || (A.start == kStartWarm && !S.warm)) {
-            u = fx;
-        } else if (A.start == kStartZero) {
-            u = 0.0;
-        } else {
-            const double dfx = (S.F[3 * a] - S.Fl[3 * a]) * X[0] +
-                               (S.F[3 * a + 1] - S.Fl[3 * a + 1]) * X[1] +
-                               (S.F[3 * a + 2] - S.Fl[3 * a + 2]) * X[2];
-            u = A.u[3 * gi + a] + dfx;
-        }
-        x[a] = X[a] + u;
+    for (int t = 0; t < C; ++t) {
+        const float X0 = c[t].dx, X1 = c[t].dy, X2 = c[t].dz;
+        const float f0 = af.F[0] * X0 + af.F[1] * X1 + af.F[2] * X2;
+        const float f1 = af.F[3] * X0 + af.F[4] * X1 + af.F[5] * X2;
+        const float f2 = af.F[6] * X0 + af.F[7] * X1 + af.F[8] * X2;
+        const float eaff = af.C[0] * X0 * X0 + af.C[1] * X1 * X1 + af.C[2] * X2 * X2 +
+                           af.C[3] * X0 * X1 + af.C[4] * X0 * X2 + af.C[5] * X1 * X2;
+        const float ex = eaff + 2.0f * (f0 * dq0[t] + f1 * dq1[t] + f2 * dq2[t]) +
+                         (dq0[t] * dq0[t] + dq1[t] * dq1[t] + dq2[t] * dq2[t]);
+        const float dx = f0 + dq0[t], dy = f1 + dq1[t], dz = f2 + dq2[t];
+        const float l2 = dx * dx + dy * dy + dz * dz;
+        float s = c[t].k * ex * rsqrtf(l2);
+        s = (k0 + t < d) ? s : 0.0f;
+        gx += s * dx; gy += s * dy; gz += s * dz;
     }
 }
 
-// Displacement written back for node r at the end of a solve.
-__device__ __forceinline__ void write_u(const SolveArgs &A, const Solve &S, int r, const double x[3])
+__device__ __forceinline__ Aff32 make_aff32(const double *F)
+{
+    Aff32 a;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a.F[k] = (float)F[k];
+    double C[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            C[p][q] = F[p] * F[q] + F[3 + p] * F[3 + q] + F[6 + p] * F[6 + q] - (p == q ? 1.0 : 0.0);
+    a.C[0] = (float)C[0][0]; a.C[1] = (float)C[1][1]; a.C[2] = (float)C[2][2];
+    a.C[3] = (float)(2.0 * C[0][1]); a.C[4] = (float)(2.0 * C[0][2]); a.C[5] = (float)(2.0 * C[1][2]);
+    return a;
+}
+
+template <class P, int CH, class Pos, class T = typename P::T>
+__device__ __forceinline__ void gather(const SolveArgs &A, const Aff32 &af, const Row &row,
+                                       const Pos &pos, int lane, int d, T qi0, T qi1, T qi2,
+                                       T &gx, T &gy, T &gz)
+{
+    static_assert(CH == 2 || CH == 4, "chunk of 2 or 4 incidences");
+    gx = 0; gy = 0; gz = 0;
+    int64_t e = row.e0 + lane;
+    int k0 = 0;
+    if constexpr (P::kDisp) {
+        for (; k0 + CH <= row.width; k0 += CH, e += CH * kWave)
+            chunk32<CH>(A, af, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz);
+        if (CH == 4 && k0 + 2 <= row.width) {
+            chunk32<2>(A, af, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz);
+            k0 += 2;
+            e += 2 * kWave;
+        }
+        if (k0 < row.width) chunk32<1>(A, af, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz);
+    } else {
+        for (; k0 + CH <= row.width; k0 += CH, e += CH * kWave)
+            chunk64<CH, false>(A, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz, nullptr);
+        if (CH == 4 && k0 + 2 <= row.width) {
+            chunk64<2, false>(A, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz, nullptr);
+            k0 += 2;
+            e += 2 * kWave;
+        }
+        if (k0 < row.width) chunk64<1, false>(A, e, pos, k0, d, qi0, qi1, qi2, gx, gy, gz, nullptr);
+    }
+}
+
+// FP64 gather that also accumulates 1/2 (T / l) d (x) d into the fiber
+// stress (each fiber is visited from both ends).
+template <class Pos>
+__device__ __forceinline__ void gather_stress(const SolveArgs &A, const Row &row, const Pos &pos,
+                                              int lane, int d, double xi, double yi, double zi,
+                                              double &gx, double &gy, double &gz, double *sf)
+{
+    gx = 0.0; gy = 0.0; gz = 0.0;
+    int64_t e = row.e0 + lane;
+    int k0 = 0;
+    for (; k0 + 2 <= row.width; k0 += 2, e += 2 * kWave)
+        chunk64<2, true>(A, e, pos, k0, d, xi, yi, zi, gx, gy, gz, sf);
+    if (k0 < row.width) chunk64<1, true>(A, e, pos, k0, d, xi, yi, zi, gx, gy, gz, sf);
+}
+
+// ---------------------------------------------------------------------------
+// Per-slot set-up shared by the kernels
+// ---------------------------------------------------------------------------
+struct Slot {
+    ProbDesc P;
+    int slot, p, start; // start: dr_start of a new solve, or kResume
+    double F[9];
+};
+
+__device__ __forceinline__ Slot load_slot(const SolveArgs &A, int slot)
+{
+    Slot S;
+    S.slot = slot;
+    S.p = A.ids ? A.ids[slot] : slot;
+    S.P = A.probs[S.p];
+    S.start = A.starts ? A.starts[slot] : A.start;
+    const double *F = (S.start == kResume) ? A.F_cur + 9 * (int64_t)S.p : A.F + 9 * (int64_t)slot;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S.F[k] = F[k];
+    return S;
+}
+
+// ((F - I) X)_a
+__device__ __forceinline__ double affine_u(const double *F, const double *X, int a)
+{
+    return (F[3 * a] - (a == 0 ? 1.0 : 0.0)) * X[0] + (F[3 * a + 1] - (a == 1 ? 1.0 : 0.0)) * X[1] +
+           (F[3 * a + 2] - (a == 2 ? 1.0 : 0.0)) * X[2];
+}
+
+// Start displacement of local node r (Fig. 1 step 4 and the initialisation):
+// prescribed nodes u = (F - I) X; free nodes from the affine field, from
+// u = 0, or warm (u_prev + (F - F_prev) X).
+__device__ __forceinline__ void start_u(const SolveArgs &A, const Slot &S, int r, double u[3])
 {
     const int64_t gi = S.P.node_base + r;
     const double X[3] = {A.X[3 * gi], A.X[3 * gi + 1], A.X[3 * gi + 2]};
-    if (r < S.P.N_free) {
+    const bool warm = S.start == kStartWarm && A.has_state[S.p];
+    const double *Fl = A.F_last + 9 * (int64_t)S.p;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) A.u[3 * gi + a] = x[a] - X[a];
-    } else {
+    for (int a = 0; a < 3; ++a) {
+        if (r >= S.P.N_free || S.start == kStartAffine || (S.start == kStartWarm && !warm)) {
+            u[a] = affine_u(S.F, X, a);
+        } else if (S.start == kStartZero) {
+            u[a] = 0.0;
+        } else {
+            const double dfx = (S.F[3 * a] - Fl[3 * a]) * X[0] +
+                               (S.F[3 * a + 1] - Fl[3 * a + 1]) * X[1] +
+                               (S.F[3 * a + 2] - Fl[3 * a + 2]) * X[2];
+            u[a] = A.u[3 * gi + a] + dfx;
+        }
+    }
+}
+
+// State q of node r at the start of a solve: the position (FP64) or the
+// displacement beyond the affine field (FP32, exactly zero on prescribed
+// nodes and for the affine start).
+template <class P, class T = typename P::T>
+__device__ __forceinline__ void start_q(const SolveArgs &A, const Slot &S, int r, T q[3])
+{
+    double u[3];
+    start_u(A, S, r, u);
+    const int64_t gi = S.P.node_base + r;
+    const double X[3] = {A.X[3 * gi], A.X[3 * gi + 1], A.X[3 * gi + 2]};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            A.u[3 * gi + a] = (S.F[3 * a] - (a == 0 ? 1.0 : 0.0)) * X[0] +
-                              (S.F[3 * a + 1] - (a == 1 ? 1.0 : 0.0)) * X[1] +
-                              (S.F[3 * a + 2] - (a == 2 ? 1.0 : 0.0)) * X[2];
+    for (int a = 0; a < 3; ++a)
+        q[a] = P::kDisp ? (T)(u[a] - affine_u(S.F, X, a)) : (T)(X[a] + u[a]);
+}
+
+// Displacement written back for node r at the end of a solve (prescribed
+// nodes get their exact affine value).
+template <class P, class T = typename P::T>
+__device__ __forceinline__ void write_u(const SolveArgs &A, const Slot &S, int r, const T q[3])
+{
+    const int64_t gi = S.P.node_base + r;
+    const double X[3] = {A.X[3 * gi], A.X[3 * gi + 1], A.X[3 * gi + 2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double u;
+        if (r < S.P.N_free) u = P::kDisp ? (double)q[a] + affine_u(S.F, X, a) : (double)q[a] - X[a];
+        else u = affine_u(S.F, X, a);
+        A.u[3 * gi + a] = u;
     }
 }
 
@@ -237,10 +413,11 @@ __device__ __forceinline__ void block_sum3(double *red, int lane, int wave, doub
 }
 
 // Residual and stop test (Fig. 1: force residual, iteration count, until
-// converged).  Returns true when the loop must end.
+// converged), plus the optional stall guard.  Returns true when the solve is
+// finished.
 __device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P, double gf2,
                                           double gb2, double ke2, int64_t n, double &rho,
-                                          double &ke, int &status)
+                                          double &ke, int &status, Progress &pg)
 {
     double den = sqrt(gb2);
     if (den < P.s_floor) den = P.s_floor;
@@ -249,101 +426,146 @@ __device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P,
     if (!isfinite(rho) || !isfinite(ke)) { status = kNonFinite; return true; }
     if (rho <= A.tol) { status = kConverged; return true; }
     if (n >= A.max_iter) { status = kMaxIter; return true; }
+    if (rho < pg.best * (1.0 - 1e-3)) {
+        pg.best = rho;
+        pg.nbest = n;
+    } else if (A.stall_window > 0 && n - pg.nbest >= A.stall_window) {
+        status = kStatusStalled;
+        return true;
+    }
     return false;
 }
 
-// End of a solve: iteration count, residual, energy and status of the slot,
-// and the state kept for a warm start (thread 0 writes).
-__device__ __forceinline__ void finish_solve(const SolveArgs &A, const Solve &S, int tid, int64_t n,
-                                             double rho, double ke, int status)
+// Scalars of the problem after a launch (thread 0 writes).
+__device__ __forceinline__ void record(const SolveArgs &A, const Slot &S, int64_t n, double rho,
+                                       double ke, int status, const Progress &pg)
 {
-    if (tid == 0) {
-        A.iters[S.slot] = n;
-        A.rho[S.slot] = rho;
-        A.ke[S.slot] = ke;
-        A.status[S.slot] = status;
+    A.iters[S.p] = n;
+    A.rho_best[S.p] = pg.best;
+    A.n_best[S.p] = pg.nbest;
+    A.rho[S.p] = rho;
+    A.ke[S.p] = ke;
+    A.status[S.p] = status;
+    if (status != kStatusRunning) {
         for (int k = 0; k < 9; ++k) A.F_last[9 * (int64_t)S.p + k] = S.F[k];
         A.has_state[S.p] = 1;
     }
 }
 
-__device__ __forceinline__ void fc0_of(const double *F, double fc0[3])
+// Start of a new solve: F of the solve kept for resumes and the stress.
+__device__ __forceinline__ void begin_solve(const SolveArgs &A, const Slot &S)
 {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) fc0[a] = 0.5 * (F[3 * a] + F[3 * a + 1] + F[3 * a + 2]);
+    for (int k = 0; k < 9; ++k) A.F_cur[9 * (int64_t)S.p + k] = S.F[k];
+    A.status[S.p] = kStatusRunning;
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident variant: positions in LDS, the half-step velocity and the
-// degree of each owned node in registers (7 VGPRs per node); 1/m and m are
-// re-read from L2 every pass.
+// Register-resident variant
 // ---------------------------------------------------------------------------
-template <int BLOCK, int NPT>
+template <class Prec, int BLOCK, int NPT, int CH>
 __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 {
+    using T = typename Prec::T;
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const Solve S = load_solve(A);
+    const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
+    // a resume of a solve that is not running is a no-op (uniform per workgroup)
+    if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
+    const Aff32 af = make_aff32(S.F);
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
     double *red = smem;
-    const LdsPos pos{smem + NW * kRedStride, smem + NW * kRedStride + N,
-                     smem + NW * kRedStride + 2 * N};
-    const double dt = P.dt, hdt = 0.5 * P.dt, cdamp = P.c;
-    const double *invm = A.invm + P.node_base;
-    const double *mass = A.mass + P.node_base;
+    const LdsQ<T> pos{reinterpret_cast<T *>(smem + NW * kRedStride), N};
+    const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
+    const int64_t nb = P.node_base;
+    constexpr int QS = kQStride<T>;
+    T *qsave = reinterpret_cast<T *>(A.qbuf) + QS * nb;
+    T *wsave = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
 
-    double w[NPT][3];
+    T w[NPT][3];
+    T cmp[NPT][3]; // compensation of the FP32 state updates (unused in FP64)
     int dg[NPT];
+    int64_t n = 0;
+    if (S.start != kResume) {
 #pragma unroll
-    for (int s = 0; s < NPT; ++s) {
-        const int r = s * BLOCK + tid;
-        w[s][0] = w[s][1] = w[s][2] = 0.0;
-        dg[s] = 0;
-        if (r < N) {
-            double x[3];
-            start_position(A, S, r, x);
-            pos.store(r, x[0], x[1], x[2]);
-            dg[s] = A.deg[P.node_base + r];
+        for (int s = 0; s < NPT; ++s) {
+            const int r = s * BLOCK + tid;
+            w[s][0] = w[s][1] = w[s][2] = 0;
+            cmp[s][0] = cmp[s][1] = cmp[s][2] = 0;
+            dg[s] = 0;
+            if (r < N) {
+                T q[3];
+                start_q<Prec>(A, S, r, q);
+                pos.store(r, q[0], q[1], q[2]);
+                dg[s] = A.deg[nb + r];
+            }
         }
-    }
-    __syncthreads();
-    // Initial internal force and acceleration (v = 0), then the first
-    // partial velocity update of the loop: w = 0 + dt/2 a.
+        if (tid == 0) begin_solve(A, S);
+        __syncthreads();
+        // Initial internal force and acceleration (v = 0), then the first
+        // partial velocity update of the loop: w = 0 + dt/2 a.
 #pragma unroll
-    for (int s = 0; s < NPT; ++s) {
-        const int r = s * BLOCK + tid;
-        // the wave's slice exists only if its first node does
-        if (s * BLOCK + wave * kWave < Nf) {
-            const Row row = node_row(A, P, r);
-            if (r < Nf) {
-                double xi, yi, zi, gx, gy, gz;
-                pos.load(r, xi, yi, zi);
-                gather_force(A, row, pos, lane, dg[s], xi, yi, zi, gx, gy, gz);
-                const double im = invm[r];
-                w[s][0] = hdt * (gx * im);
-                w[s][1] = hdt * (gy * im);
-                w[s][2] = hdt * (gz * im);
+        for (int s = 0; s < NPT; ++s) {
+            const int r = s * BLOCK + tid;
+            // the wave's slice exists only if its first node does
+            if (s * BLOCK + wave * kWave < Nf) {
+                const Row row = node_row(A, P, r);
+                if (r < Nf) {
+                    T qi[3], g[3];
+                    pos.load(r, qi[0], qi[1], qi[2]);
+                    gather<Prec, CH>(A, af, row, pos, lane, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
+                    const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) w[s][a] = hdt * (g[a] * im);
+                }
+            }
+        }
+    } else {
+        n = A.iters[S.p];
+#pragma unroll
+        for (int s = 0; s < NPT; ++s) {
+            const int r = s * BLOCK + tid;
+            w[s][0] = w[s][1] = w[s][2] = 0;
+            cmp[s][0] = cmp[s][1] = cmp[s][2] = 0;
+            dg[s] = 0;
+            if (r < N) {
+                pos.store(r, qsave[QS * r], qsave[QS * r + 1], qsave[QS * r + 2]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    w[s][a] = wsave[4 * r + a];
+                    if constexpr (Prec::kDisp) cmp[s][a] = qsave[QS * r + 4 + a];
+                }
+                dg[s] = A.deg[nb + r];
             }
         }
     }
     __syncthreads();
 
-    int64_t n = 0;
+    const int64_t n0 = n;
     double rho = 0.0, ke = 0.0;
-    int status = kMaxIter;
+    int status = kStatusRunning;
+    Progress pg{__builtin_huge_val(), n};
+    if (S.start == kResume) {
+        pg.best = A.rho_best[S.p];
+        pg.nbest = A.n_best[S.p];
+    }
     for (;;) {
+        // An opaque copy of the thread index: everything derived from it
+        // (node ids, addresses) is recomputed each pass instead of being held
+        // in registers across the loop, which would spill at 1024 threads.
+        int tp = tid;
+        asm volatile("" : "+v"(tp));
         // displacement update (free dof)
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
-            const int r = s * BLOCK + tid;
+            const int r = s * BLOCK + tp;
             if (r < Nf) {
-                double x, y, z;
+                T x, y, z;
                 pos.load(r, x, y, z);
-                x += dt * w[s][0];
-                y += dt * w[s][1];
-                z += dt * w[s][2];
+                advance_q(x, dt * w[s][0], cmp[s][0]);
+                advance_q(y, dt * w[s][1], cmp[s][1]);
+                advance_q(z, dt * w[s][2], cmp[s][2]);
                 pos.store(r, x, y, z);
             }
         }
@@ -351,27 +573,29 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
-            const int r = s * BLOCK + tid;
+            const int r = s * BLOCK + tp;
             if (s * BLOCK + wave * kWave < N) {
                 const Row row = node_row(A, P, r);
                 if (r < N) {
-                    double xi, yi, zi, g[3];
-                    pos.load(r, xi, yi, zi);
-                    gather_force(A, row, pos, lane, dg[s], xi, yi, zi, g[0], g[1], g[2]);
-                    const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+                    T qi[3], g[3];
+                    pos.load(r, qi[0], qi[1], qi[2]);
+                    gather<Prec, CH>(A, af, row, pos, lane, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
+                    const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
+                                      (double)g[2] * (double)g[2];
                     if (r < Nf) {
-                        const double im = invm[r];
+                        const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+                        const double m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
                         double vv = 0.0;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             // damping force, acceleration, partial velocity updates
-                            const double acc = g[a] * im - cdamp * w[s][a];
-                            const double v = w[s][a] + hdt * acc;
-                            vv += v * v;
+                            const T acc = g[a] * im - cdamp * w[s][a];
+                            const T v = w[s][a] + hdt * acc;
+                            vv += (double)v * (double)v;
                             w[s][a] = v + hdt * acc;
                         }
                         gf2 += gg;
-                        ke2 += mass[r] * vv;
+                        ke2 += m * vv;
                     } else {
                         gb2 += gg;
                     }
@@ -380,148 +604,253 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         }
         block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
         ++n;
-        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status)) break;
+        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status, pg)) break;
+        if (n - n0 >= A.budget) break;
     }
 
-    // Displacements of the final iterate (the stress kernel reads them).
+    if (status != kStatusRunning) {
 #pragma unroll
-    for (int s = 0; s < NPT; ++s) {
-        const int r = s * BLOCK + tid;
-        if (r < N) {
-            double x[3];
-            pos.load(r, x[0], x[1], x[2]);
-            write_u(A, S, r, x);
+        for (int s = 0; s < NPT; ++s) {
+            const int r = s * BLOCK + tid;
+            if (r < N) {
+                T q[3];
+                pos.load(r, q[0], q[1], q[2]);
+                write_u<Prec>(A, S, r, q);
+            }
+        }
+    } else {
+        // budget spent: save the exact state for the next launch
+#pragma unroll
+        for (int s = 0; s < NPT; ++s) {
+            const int r = s * BLOCK + tid;
+            if (r < N) {
+                T q[3];
+                pos.load(r, q[0], q[1], q[2]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    qsave[QS * r + a] = q[a];
+                    wsave[4 * r + a] = w[s][a];
+                    if constexpr (Prec::kDisp) qsave[QS * r + 4 + a] = cmp[s][a];
+                }
+            }
         }
     }
-    finish_solve(A, S, tid, n, rho, ke, status);
+    if (tid == 0) record(A, S, n, rho, ke, status, pg);
 }
 
 // ---------------------------------------------------------------------------
-// Global-placement variant: positions and half-step velocities in device
-// memory (L2-resident for one problem), any problem size.
+// Global-placement variant: state and half-step velocities in device memory
+// (L2-resident for one problem), any problem size.
 // ---------------------------------------------------------------------------
-template <int BLOCK>
+template <class Prec, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
 {
+    using T = typename Prec::T;
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const Solve S = load_solve(A);
+    const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
+    // a resume of a solve that is not running is a no-op (uniform per workgroup)
+    if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
+    const Aff32 af = make_aff32(S.F);
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
     double *red = smem;
-    const GlbPos pos{A.xg + 4 * P.node_base};
-    double *W = A.wg + 4 * P.node_base;
-    const double dt = P.dt, hdt = 0.5 * P.dt, cdamp = P.c;
-
-    for (int r = tid; r < N; r += BLOCK) {
-        double x[3];
-        start_position(A, S, r, x);
-        pos.store(r, x[0], x[1], x[2]);
-    }
-    __syncthreads();
-    for (int r = tid; r < Nf; r += BLOCK) {
-        double xi, yi, zi, gx, gy, gz;
-        pos.load(r, xi, yi, zi);
-        const double imr = A.invm[P.node_base + r];
-        gather_force(A, node_row(A, P, r), pos, lane, A.deg[P.node_base + r], xi, yi, zi, gx, gy,
-                     gz);
-        W[4 * r + 0] = hdt * (gx * imr);
-        W[4 * r + 1] = hdt * (gy * imr);
-        W[4 * r + 2] = hdt * (gz * imr);
-    }
-    __syncthreads();
+    const int64_t nb = P.node_base;
+    constexpr int QS = kQStride<T>;
+    const GlbQ<T> pos{reinterpret_cast<T *>(A.qbuf) + QS * nb};
+    T *Cq = reinterpret_cast<T *>(A.qbuf) + QS * nb + 4; // FP32 compensation terms
+    T *W = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
+    const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
 
     int64_t n = 0;
+    if (S.start != kResume) {
+        for (int r = tid; r < N; r += BLOCK) {
+            T q[3];
+            start_q<Prec>(A, S, r, q);
+            pos.store(r, q[0], q[1], q[2]);
+            if constexpr (Prec::kDisp)
+                for (int a = 0; a < 3; ++a) Cq[QS * r + a] = 0;
+        }
+        if (tid == 0) begin_solve(A, S);
+        __syncthreads();
+        for (int r = tid; r < Nf; r += BLOCK) {
+            T qi[3], g[3];
+            pos.load(r, qi[0], qi[1], qi[2]);
+            gather<Prec, 4>(A, af, node_row(A, P, r), pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
+                         g[1], g[2]);
+            const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) W[4 * r + a] = hdt * (g[a] * im);
+        }
+    } else {
+        n = A.iters[S.p];
+    }
+    __syncthreads();
+
+    const int64_t n0 = n;
     double rho = 0.0, ke = 0.0;
-    int status = kMaxIter;
+    int status = kStatusRunning;
+    Progress pg{__builtin_huge_val(), n};
+    if (S.start == kResume) {
+        pg.best = A.rho_best[S.p];
+        pg.nbest = A.n_best[S.p];
+    }
     for (;;) {
         for (int r = tid; r < Nf; r += BLOCK) {
-            double x, y, z;
-            pos.load(r, x, y, z);
-            x += dt * W[4 * r + 0];
-            y += dt * W[4 * r + 1];
-            z += dt * W[4 * r + 2];
-            pos.store(r, x, y, z);
+            T q[3], c[3] = {0, 0, 0};
+            pos.load(r, q[0], q[1], q[2]);
+            if constexpr (Prec::kDisp)
+                for (int a = 0; a < 3; ++a) c[a] = Cq[QS * r + a];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) advance_q(q[a], dt * W[4 * r + a], c[a]);
+            pos.store(r, q[0], q[1], q[2]);
+            if constexpr (Prec::kDisp)
+                for (int a = 0; a < 3; ++a) Cq[QS * r + a] = c[a];
         }
         __syncthreads();
         double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
         for (int r = tid; r < N; r += BLOCK) {
-            double xi, yi, zi, g[3];
-            pos.load(r, xi, yi, zi);
-            gather_force(A, node_row(A, P, r), pos, lane, A.deg[P.node_base + r], xi, yi, zi,
-                         g[0], g[1], g[2]);
-            const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+            T qi[3], g[3];
+            pos.load(r, qi[0], qi[1], qi[2]);
+            gather<Prec, 4>(A, af, node_row(A, P, r), pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
+                         g[1], g[2]);
+            const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
+                              (double)g[2] * (double)g[2];
             if (r < Nf) {
-                const double imr = A.invm[P.node_base + r];
+                const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+                const double m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
                 double vv = 0.0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double wa = W[4 * r + a];
-                    const double acc = g[a] * imr - cdamp * wa;
-                    const double v = wa + hdt * acc;
-                    vv += v * v;
+                    const T wa = W[4 * r + a];
+                    const T acc = g[a] * im - cdamp * wa;
+                    const T v = wa + hdt * acc;
+                    vv += (double)v * (double)v;
                     W[4 * r + a] = v + hdt * acc;
                 }
                 gf2 += gg;
-                ke2 += A.mass[P.node_base + r] * vv;
+                ke2 += m * vv;
             } else {
                 gb2 += gg;
             }
         }
         block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
         ++n;
-        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status)) break;
+        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status, pg)) break;
+        if (n - n0 >= A.budget) break;
     }
 
-    for (int r = tid; r < N; r += BLOCK) {
-        double x[3];
-        pos.load(r, x[0], x[1], x[2]);
-        write_u(A, S, r, x);
+    if (status != kStatusRunning) {
+        for (int r = tid; r < N; r += BLOCK) {
+            T q[3];
+            pos.load(r, q[0], q[1], q[2]);
+            write_u<Prec>(A, S, r, q);
+        }
     }
-    finish_solve(A, S, tid, n, rho, ke, status);
+    if (tid == 0) record(A, S, n, rho, ke, status, pg);
+}
+
+// ---------------------------------------------------------------------------
+// Stress average (section I: the sub-problem returns the volume-averaged
+// stress to the macroscale), one workgroup per slot whose solve has finished,
+// FP64, from the final displacements:
+//   sigma     = 1/J sum over prescribed nodes of (-g_b) (x) (x_b - F c0)
+//   sigma_fib = 1/J sum over fibers of T d (x) d / l
+// ---------------------------------------------------------------------------
+struct UPos {
+    const double *X, *u; // renumbered, 3 per node, offset to the problem
+    __device__ __forceinline__ void load(int j, double &x, double &y, double &z) const
+    {
+        x = X[3 * (int64_t)j] + u[3 * (int64_t)j];
+        y = X[3 * (int64_t)j + 1] + u[3 * (int64_t)j + 1];
+        z = X[3 * (int64_t)j + 2] + u[3 * (int64_t)j + 2];
+    }
+};
+
+constexpr int kStressBlock = 256;
+
+__global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
+{
+    __shared__ double red[(kStressBlock / kWave) * kRedStride];
+    constexpr int NW = kStressBlock / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int slot = slot0 + (int)blockIdx.x;
+    const int p = A.ids ? A.ids[slot] : slot;
+    const int st = A.status[p];
+    if (st == kStatusRunning || st == kStatusIdle) return; // uniform over the workgroup
+    const ProbDesc P = A.probs[p];
+    double F[9];
+    for (int k = 0; k < 9; ++k) F[k] = A.F_cur[9 * (int64_t)p + k];
+    const UPos pos{A.X + 3 * P.node_base, A.u + 3 * P.node_base};
+    double fc0[3];
+    for (int a = 0; a < 3; ++a) fc0[a] = 0.5 * (F[3 * a] + F[3 * a + 1] + F[3 * a + 2]);
+    double sb[9], sf[9];
+    for (int k = 0; k < 9; ++k) { sb[k] = 0.0; sf[k] = 0.0; }
+    for (int r = tid; r < P.N; r += kStressBlock) {
+        double x[3], g[3];
+        pos.load(r, x[0], x[1], x[2]);
+        gather_stress(A, node_row(A, P, r), pos, lane, A.deg[P.node_base + r], x[0], x[1], x[2],
+                      g[0], g[1], g[2], sf);
+        if (r >= P.N_free) {
+            const double y[3] = {x[0] - fc0[0], x[1] - fc0[1], x[2] - fc0[2]};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) sb[3 * a + b] -= g[a] * y[b];
+        }
+    }
+    for (int k = 0; k < 9; ++k) { sb[k] = wave_sum(sb[k]); sf[k] = wave_sum(sf[k]); }
+    if (lane == 0) {
+        for (int k = 0; k < 9; ++k) {
+            red[wave * kRedStride + k] = sb[k];
+            red[wave * kRedStride + 9 + k] = sf[k];
+        }
+    }
+    __syncthreads();
+    if (tid < 18) {
+        const double J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                         F[2] * (F[3] * F[7] - F[4] * F[6]);
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += red[w * kRedStride + tid];
+        if (tid < 9) A.sigma[9 * (int64_t)p + tid] = t / J;
+        else A.sigma_fib[9 * (int64_t)p + tid - 9] = t / J;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Per-problem launch loop (the paper's naive design): the same pass split
-// into kernels over nodes, with the residual read back by the host.
+// into kernels over nodes, with the residual read back by the host.  FP64;
+// the running state uses the same buffers as the global-placement kernel.
 // ---------------------------------------------------------------------------
 constexpr int kLoopBlock = 256;
 
 // phase 0: start positions; phase 1: initial acceleration -> w.
 __global__ void __launch_bounds__(kLoopBlock) k_loop_setup(SolveArgs A, int slot, int phase)
 {
-    Solve S;
-    S.slot = slot;
-    S.p = A.ids ? A.ids[slot] : slot;
-    S.P = A.probs[S.p];
-    for (int k = 0; k < 9; ++k) S.F[k] = A.F[9 * (int64_t)slot + k];
-    S.warm = (A.start == kStartWarm) && A.has_state[S.p];
-    for (int k = 0; k < 9; ++k) S.Fl[k] = S.warm ? A.F_last[9 * (int64_t)S.p + k] : S.F[k];
+    const Slot S = load_slot(A, slot);
     const ProbDesc &P = S.P;
-    const GlbPos pos{A.xg + 4 * P.node_base};
-    double *W = A.wg + 4 * P.node_base;
+    const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
+    double *W = A.wbuf + 4 * P.node_base;
     const int r = blockIdx.x * kLoopBlock + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     if (phase == 0) {
         if (r < P.N) {
-            double x[3];
-            start_position(A, S, r, x);
-            pos.store(r, x[0], x[1], x[2]);
+            double q[3];
+            start_q<P64>(A, S, r, q);
+            pos.store(r, q[0], q[1], q[2]);
         }
+        if (blockIdx.x == 0 && threadIdx.x == 0) begin_solve(A, S);
     } else {
         const int wbase = blockIdx.x * kLoopBlock + (threadIdx.x / kWave) * kWave;
         if (wbase >= P.N) return;
         const Row row = node_row(A, P, wbase);
         if (r < P.N_free) {
-            double xi, yi, zi, gx, gy, gz;
-            pos.load(r, xi, yi, zi);
-            const double imr = A.invm[P.node_base + r];
-            gather_force(A, row, pos, lane, A.deg[P.node_base + r], xi, yi, zi, gx, gy, gz);
+            double qi[3], g[3];
+            pos.load(r, qi[0], qi[1], qi[2]);
+            gather<P64, 4>(A, Aff32{}, row, pos, lane, A.deg[P.node_base + r], qi[0], qi[1], qi[2], g[0],
+                           g[1], g[2]);
+            const double im = A.invm[P.node_base + r];
             const double hdt = 0.5 * P.dt;
-            W[4 * r + 0] = hdt * (gx * imr);
-            W[4 * r + 1] = hdt * (gy * imr);
-            W[4 * r + 2] = hdt * (gz * imr);
+            for (int a = 0; a < 3; ++a) W[4 * r + a] = hdt * (g[a] * im);
         }
     }
 }
@@ -530,8 +859,8 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_update(SolveArgs A, int slo
 {
     const int p = A.ids ? A.ids[slot] : slot;
     const ProbDesc P = A.probs[p];
-    const GlbPos pos{A.xg + 4 * P.node_base};
-    const double *W = A.wg + 4 * P.node_base;
+    const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
+    const double *W = A.wbuf + 4 * P.node_base;
     const int r = blockIdx.x * kLoopBlock + threadIdx.x;
     if (r < P.N_free) {
         double x, y, z;
@@ -549,27 +878,29 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_force(SolveArgs A, int slot
     __shared__ double red[(kLoopBlock / kWave) * kRedStride];
     const int p = A.ids ? A.ids[slot] : slot;
     const ProbDesc P = A.probs[p];
-    const GlbPos pos{A.xg + 4 * P.node_base};
-    double *W = A.wg + 4 * P.node_base;
+    const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
+    double *W = A.wbuf + 4 * P.node_base;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int r = blockIdx.x * kLoopBlock + tid;
     const double hdt = 0.5 * P.dt;
     double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     const int wbase = blockIdx.x * kLoopBlock + wave * kWave;
     Row row;
-    row.e0 = 0; row.width = 0;
+    row.e0 = 0;
+    row.width = 0;
     if (wbase < P.N) row = node_row(A, P, wbase);
     if (r < P.N) {
-        double xi, yi, zi, g[3];
-        pos.load(r, xi, yi, zi);
-        gather_force(A, row, pos, lane, A.deg[P.node_base + r], xi, yi, zi, g[0], g[1], g[2]);
+        double qi[3], g[3];
+        pos.load(r, qi[0], qi[1], qi[2]);
+        gather<P64, 4>(A, Aff32{}, row, pos, lane, A.deg[P.node_base + r], qi[0], qi[1], qi[2], g[0], g[1],
+                       g[2]);
         const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
         if (r < P.N_free) {
-            const double imr = A.invm[P.node_base + r];
+            const double im = A.invm[P.node_base + r];
             double vv = 0.0;
             for (int a = 0; a < 3; ++a) {
                 const double wa = W[4 * r + a];
-                const double acc = g[a] * imr - P.c * wa;
+                const double acc = g[a] * im - P.c * wa;
                 const double v = wa + hdt * acc;
                 vv += v * v;
                 W[4 * r + a] = v + hdt * acc;
@@ -604,84 +935,22 @@ __global__ void __launch_bounds__(kWave) k_loop_reduce(const double *partial, in
 __global__ void __launch_bounds__(kLoopBlock) k_loop_finish(SolveArgs A, int slot, int64_t n,
                                                             double rho, double ke, int status)
 {
-    Solve S;
-    S.slot = slot;
-    S.p = A.ids ? A.ids[slot] : slot;
-    S.P = A.probs[S.p];
-    for (int k = 0; k < 9; ++k) S.F[k] = A.F[9 * (int64_t)slot + k];
-    for (int k = 0; k < 9; ++k) S.Fl[k] = S.F[k];
-    S.warm = false;
-    const GlbPos pos{A.xg + 4 * S.P.node_base};
+    Slot S = load_slot(A, slot);
+    for (int k = 0; k < 9; ++k) S.F[k] = A.F_cur[9 * (int64_t)S.p + k];
+    const GlbQ<double> pos{A.qbuf + 4 * S.P.node_base};
     const int r = blockIdx.x * kLoopBlock + threadIdx.x;
     if (r < S.P.N) {
-        double x[3];
-        pos.load(r, x[0], x[1], x[2]);
-        write_u(A, S, r, x);
+        double q[3];
+        pos.load(r, q[0], q[1], q[2]);
+        write_u<P64>(A, S, r, q);
     }
-    if (blockIdx.x == 0) finish_solve(A, S, threadIdx.x, n, rho, ke, status);
+    if (blockIdx.x == 0 && threadIdx.x == 0) record(A, S, n, rho, ke, status, Progress{rho, n});
 }
 
-// ---------------------------------------------------------------------------
-// Stress average (section I: the sub-problem returns the volume-averaged
-// stress to the macroscale), one workgroup per solve slot, FP64, from the
-// final displacements:
-//   sigma     = 1/J sum over prescribed nodes of (-g_b) (x) (x_b - F c0)
-//   sigma_fib = 1/J sum over fibers of T d (x) d / l
-// ---------------------------------------------------------------------------
-struct UPos {
-    const double *X, *u; // renumbered, 3 per node, offset to the problem
-    __device__ __forceinline__ void load(int j, double &x, double &y, double &z) const
-    {
-        x = X[3 * (int64_t)j] + u[3 * (int64_t)j];
-        y = X[3 * (int64_t)j + 1] + u[3 * (int64_t)j + 1];
-        z = X[3 * (int64_t)j + 2] + u[3 * (int64_t)j + 2];
-    }
-};
-
-constexpr int kStressBlock = 256;
-
-__global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
 {
-    __shared__ double red[(kStressBlock / kWave) * kRedStride];
-    constexpr int NW = kStressBlock / kWave;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int slot = slot0 + (int)blockIdx.x;
-    const int p = A.ids ? A.ids[slot] : slot;
-    const ProbDesc P = A.probs[p];
-    double F[9];
-    for (int k = 0; k < 9; ++k) F[k] = A.F[9 * (int64_t)slot + k];
-    const UPos pos{A.X + 3 * P.node_base, A.u + 3 * P.node_base};
-    double fc0[3];
-    fc0_of(F, fc0);
-    double sb[9], sf[9];
-    for (int k = 0; k < 9; ++k) { sb[k] = 0.0; sf[k] = 0.0; }
-    for (int r = tid; r < P.N; r += kStressBlock) {
-        double x[3], g[3];
-        pos.load(r, x[0], x[1], x[2]);
-        gather_force_stress(A, node_row(A, P, r), pos, lane, A.deg[P.node_base + r], x[0], x[1],
-                            x[2], g[0], g[1], g[2], sf);
-        if (r >= P.N_free) {
-            const double y[3] = {x[0] - fc0[0], x[1] - fc0[1], x[2] - fc0[2]};
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) sb[3 * a + b] -= g[a] * y[b];
-        }
-    }
-    for (int k = 0; k < 9; ++k) { sb[k] = wave_sum(sb[k]); sf[k] = wave_sum(sf[k]); }
-    if (lane == 0) {
-        for (int k = 0; k < 9; ++k) {
-            red[wave * kRedStride + k] = sb[k];
-            red[wave * kRedStride + 9 + k] = sf[k];
-        }
-    }
-    __syncthreads();
-    if (tid < 18) {
-        const double J = F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
-                         F[2] * (F[3] * F[7] - F[4] * F[6]);
-        double t = 0.0;
-        for (int w = 0; w < NW; ++w) t += red[w * kRedStride + tid];
-        if (tid < 9) A.sigma[9 * (int64_t)slot + tid] = t / J;
-        else A.sigma_fib[9 * (int64_t)slot + tid - 9] = t / J;
-    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -699,51 +968,55 @@ static int launch(K kernel, int grid, int block, int lds, hipStream_t st, const 
     return (int)hipGetLastError();
 }
 
-#define DR_REG_CASE(B, NP)                                                                       \
-    case NP:                                                                                     \
-        return launch(k_dr_reg<B, NP>, a.n_solve, B, plan.lds_bytes, st, a);
-
-template <int B>
-static int launch_reg(const SolveArgs &a, const LaunchPlan &plan, hipStream_t st)
+template <class P, int B, int NP>
+static int launch_reg_np(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
 {
-    switch (plan.npt) {
-        DR_REG_CASE(B, 1)
-        DR_REG_CASE(B, 2)
-        DR_REG_CASE(B, 3)
-        DR_REG_CASE(B, 4)
-        DR_REG_CASE(B, 5)
-        DR_REG_CASE(B, 6)
-        DR_REG_CASE(B, 7)
-        DR_REG_CASE(B, 8)
-    default:
-        return -1000;
+    if (pl.chunk == 4) return launch(k_dr_reg<P, B, NP, 4>, a.n_solve, B, pl.lds_bytes, st, a);
+    return launch(k_dr_reg<P, B, NP, 2>, a.n_solve, B, pl.lds_bytes, st, a);
+}
+
+template <class P, int B>
+static int launch_reg(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
+{
+    switch (pl.npt) {
+    case 1: return launch_reg_np<P, B, 1>(a, pl, st);
+    case 2: return launch_reg_np<P, B, 2>(a, pl, st);
+    case 3: return launch_reg_np<P, B, 3>(a, pl, st);
+    case 4: return launch_reg_np<P, B, 4>(a, pl, st);
+    case 5: return launch_reg_np<P, B, 5>(a, pl, st);
+    case 6: return launch_reg_np<P, B, 6>(a, pl, st);
+    case 7: return launch_reg_np<P, B, 7>(a, pl, st);
+    case 8: return launch_reg_np<P, B, 8>(a, pl, st);
+    default: return -1000;
     }
 }
 
-static int launch_dr(const SolveArgs &a, const LaunchPlan &plan, hipStream_t st)
+template <class P>
+static int launch_dr(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
 {
-    if (plan.npt > 0) {
-        switch (plan.block) {
-        case 256: return launch_reg<256>(a, plan, st);
-        case 512: return launch_reg<512>(a, plan, st);
-        case 1024: return launch_reg<1024>(a, plan, st);
+    if (pl.npt > 0) {
+        switch (pl.block) {
+        case 256: return launch_reg<P, 256>(a, pl, st);
+        case 512: return launch_reg<P, 512>(a, pl, st);
+        case 1024: return launch_reg<P, 1024>(a, pl, st);
         default: return -1001;
         }
     }
-    switch (plan.block) {
-    case 256: return launch(k_dr_glb<256>, a.n_solve, 256, plan.lds_bytes, st, a);
-    case 512: return launch(k_dr_glb<512>, a.n_solve, 512, plan.lds_bytes, st, a);
-    case 1024: return launch(k_dr_glb<1024>, a.n_solve, 1024, plan.lds_bytes, st, a);
+    switch (pl.block) {
+    case 256: return launch(k_dr_glb<P, 256>, a.n_solve, 256, pl.lds_bytes, st, a);
+    case 512: return launch(k_dr_glb<P, 512>, a.n_solve, 512, pl.lds_bytes, st, a);
+    case 1024: return launch(k_dr_glb<P, 1024>, a.n_solve, 1024, pl.lds_bytes, st, a);
     default: return -1001;
     }
 }
 
-// The batched solve: one persistent DR launch, then the stress launch.
+// One batched launch: the persistent DR kernel, then the stress kernel (which
+// skips the slots whose solve is still running).
 int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (a.n_solve <= 0) return 0;
-    const int rc = launch_dr(a, plan, st);
+    const int rc = plan.fp32 ? launch_dr<P32>(a, plan, st) : launch_dr<P64>(a, plan, st);
     if (rc != 0) return rc;
     hipLaunchKernelGGL(k_stress, dim3(a.n_solve), dim3(kStressBlock), 0, st, a, 0);
     return (int)hipGetLastError();
@@ -752,11 +1025,10 @@ int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream)
 // One step of the launch-loop design for solve slot `slot`:
 //   phase 0: set-up (start positions, initial acceleration)
 //   phase 1: one DR pass (update, force, reduce -> out_scalars[0..2])
-//   phase 2: displacements, scalars and stress; out_scalars[3..5] is a HOST
-//            array {rho, ke, status} passed by value to the kernels
-int launch_loop_iteration_kernels(const SolveArgs &a, int slot, int phase, int n_nodes,
-                                  double *partial, double *out_scalars, int64_t n_done,
-                                  void *stream)
+//   phase 2: displacements, scalars and stress of the finished solve
+int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, double *partial,
+                        double *out_scalars, int64_t n_done, double rho, double ke, int status,
+                        void *stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int nblk = (n_nodes + kLoopBlock - 1) / kLoopBlock;
@@ -769,9 +1041,18 @@ int launch_loop_iteration_kernels(const SolveArgs &a, int slot, int phase, int n
         hipLaunchKernelGGL(k_loop_reduce, dim3(1), dim3(kWave), 0, st, partial, nblk, out_scalars);
     } else {
         hipLaunchKernelGGL(k_loop_finish, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, n_done,
-                           out_scalars[3], out_scalars[4], (int)out_scalars[5]);
+                           rho, ke, status);
         hipLaunchKernelGGL(k_stress, dim3(1), dim3(kStressBlock), 0, st, a, slot);
     }
+    return (int)hipGetLastError();
+}
+
+int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n);
     return (int)hipGetLastError();
 }
 

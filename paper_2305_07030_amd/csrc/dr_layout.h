@@ -13,13 +13,25 @@
 // holds width_q * 64 entries, entry (k, lane) at slice_off[q] + k * 64 + lane,
 // k < width_q = the largest degree in the slice.  Within a node the
 // incidences follow ascending fiber id.  Each entry carries the neighbour's
-// local id and the fiber constants {EA / (2 L^2), L^2}.
+// local id and the fiber constants: {EA / (2 L^2), L^2} in FP64, and for the
+// FP32 state {dX (the reference vector to the neighbour), EA / (2 L^2)}.
+// Padding entries hold neighbour 0 and zero constants.
 #pragma once
 #include <stdint.h>
 
 namespace drk {
 
 constexpr int kWave = 64;
+
+// Per-problem status values beyond dr_result: a solve that has been started
+// and stopped at a pass budget, and a problem with no solve yet.
+constexpr int kStatusRunning = 3;
+constexpr int kStatusIdle = 4;
+constexpr int kStatusStalled = 5;
+
+// Slot start codes: a dr_start value starts a new solve; kResume continues
+// the problem's running solve from the state saved in HBM.
+constexpr int kResume = -1;
 
 struct ProbDesc {
     int32_t N;          // nodes
@@ -41,39 +53,53 @@ struct KL {
     double L2; // L^2
 };
 
-// Arguments of one batched solve (passed by value as the kernel argument).
+struct KL32 {
+    float dx, dy, dz; // X_neighbour - X_node
+    float k;          // EA / (2 L^2)
+};
+
+// Arguments of one batched launch (passed by value as the kernel argument).
 struct SolveArgs {
     const ProbDesc *probs;    // [P]
-    const int32_t *ids;       // [n_solve] problem of each solve slot (NULL: slot = problem)
+    const int32_t *ids;       // [n_solve] problem of each slot (NULL: slot = problem)
     const int32_t *order;     // [n_solve] launch order of the slots (NULL: identity)
-    const double *F;          // [n_solve * 9]
+    const int32_t *starts;    // [n_solve] dr_start of a new solve, or kResume (NULL: start)
+    const double *F;          // [n_solve * 9] F of the slots that start a solve
     int32_t n_solve;
-    int32_t start;            // dr_start
+    int32_t start;            // dr_start used when starts == NULL
     double tol;
-    int64_t max_iter;
+    int64_t max_iter;         // cap on the passes of one solve
+    int64_t budget;           // cap on the passes made in this launch
+    int64_t stall_window;     // 0 = off, else passes without progress that end a solve
     // network (renumbered order)
     const double *X;          // [nodes * 3]
     const double *invm;       // [nodes]
     const double *mass;       // [nodes]
+    const float *invm32;      // [nodes] (FP32 state)
+    const float *mass32;      // [nodes] (FP32 state)
     const int32_t *deg;       // [nodes]
     const int32_t *slice_w;   // [slices]
     const int64_t *slice_off; // [slices], relative to the problem's inc_base
     const int32_t *nbr;       // [incidences]
     const KL *kl;             // [incidences]
-    // state kept on the device between solves
-    double *u;                // [nodes * 3] displacement (renumbered)
-    double *F_last;           // [P * 9] F of the last solve of each problem
-    int32_t *has_state;       // [P] 1 once a solve has written u
-    // scratch for the global-placement kernel
-    double *xg;               // [nodes * 4] positions (x, y, z, pad)
-    double *wg;               // [nodes * 4] half-step velocities
-    // results, per solve slot
-    double *sigma;            // [n_solve * 9]
-    double *sigma_fib;        // [n_solve * 9]
-    int64_t *iters;           // [n_solve]
-    double *rho;              // [n_solve]
-    double *ke;               // [n_solve]
-    int32_t *status;          // [n_solve]
+    const KL32 *kl32;         // [incidences] (FP32 state)
+    // state kept on the device
+    double *u;                // [nodes * 3] displacement of the last finished solve
+    double *qbuf;             // [nodes * 4] running state: positions (FP64) or
+                              //   displacements (FP32), 4 values per node
+    double *wbuf;             // [nodes * 4] running half-step velocities
+    double *F_cur;            // [P * 9] F of the current solve
+    double *F_last;           // [P * 9] F of the last finished solve
+    int32_t *has_state;       // [P] 1 once a solve has finished
+    // results, per problem
+    double *sigma;            // [P * 9]
+    double *sigma_fib;        // [P * 9]
+    int64_t *iters;           // [P] passes of the current / last solve
+    double *rho_best;         // [P] best residual of the running solve (stall guard)
+    int64_t *n_best;          // [P] pass at which it was reached
+    double *rho;              // [P]
+    double *ke;               // [P]
+    int32_t *status;          // [P] dr_result, kStatusRunning or kStatusIdle
 };
 
 // Launch shape of one batched solve.
@@ -81,13 +107,16 @@ struct LaunchPlan {
     int block;     // threads per workgroup
     int npt;       // nodes per thread (register-resident variant), 0 = global
     int lds_bytes; // dynamic LDS per workgroup
+    int chunk;     // incidences gathered per unconditional chunk (2 or 4)
+    int fp32;      // 1: FP32 nodal state and force gather
 };
 
 // Implemented in dr_kernels.hip.
 int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream);
-int launch_loop_iteration_kernels(const SolveArgs &a, int slot, int phase, int n_nodes,
-                                  double *partial, double *out_scalars, int64_t n_done,
-                                  void *stream);
+int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, double *partial,
+                        double *out_scalars, int64_t n_done, double rho, double ke, int status,
+                        void *stream);
+int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream);
 const char *kernel_error_string(int code);
 
 } // namespace drk

@@ -15,9 +15,9 @@ import numpy as np
 from . import build as _build
 
 DR_OK, DR_E_INVALID, DR_E_NOMEM, DR_E_DEVICE, DR_E_STATE = 0, -1, -2, -3, -4
-DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE = 0, 1, 2
+DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE, DR_RUNNING, DR_IDLE, DR_STALLED = 0, 1, 2, 3, 4, 5
 DR_FP64, DR_FP32 = 0, 1
-DR_START_AFFINE, DR_START_ZERO, DR_START_WARM = 0, 1, 2
+DR_RESUME, DR_START_AFFINE, DR_START_ZERO, DR_START_WARM = -1, 0, 1, 2
 DR_PLACE_AUTO, DR_PLACE_LDS, DR_PLACE_GLOBAL = 0, 1, 2
 
 _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
@@ -25,8 +25,8 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 
 # Every exported symbol of include/dr.h.
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
-           "dr_stress", "dr_sync", "dr_solve_loop", "dr_batch_info", "dr_batch_scalars",
-           "dr_batch_destroy", "dr_last_error")
+           "dr_stress", "dr_advance", "dr_results", "dr_sync", "dr_solve_loop", "dr_batch_info",
+           "dr_batch_scalars", "dr_batch_destroy", "dr_last_error")
 
 
 class DrError(RuntimeError):
@@ -52,7 +52,9 @@ class dr_options(C.Structure):
                 ("damping", C.c_double),
                 ("dt_safety", C.c_double),
                 ("block", C.c_int32),
-                ("placement", C.c_int32)]
+                ("placement", C.c_int32),
+                ("chunk", C.c_int32),
+                ("stall_window", C.c_int64)]
 
 
 _lib = None
@@ -82,6 +84,10 @@ def load():
     lib.dr_solve_device.restype = C.c_int
     lib.dr_stress.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.dr_stress.restype = C.c_int
+    lib.dr_advance.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64]
+    lib.dr_advance.restype = C.c_int
+    lib.dr_results.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.dr_results.restype = C.c_int
     lib.dr_sync.argtypes = [vp]
     lib.dr_sync.restype = C.c_int
     lib.dr_solve_loop.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
@@ -158,9 +164,29 @@ def dr_solve(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int
     _check(load().dr_solve(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
 
 
-def dr_solve_device(h: int, F_device_ptr: int, ids_device_ptr: Optional[int], n_ids: int,
+def dr_solve_device(h: int, F_device_ptr: int, ids: Optional[np.ndarray], n_ids: int,
                     start: int = DR_START_AFFINE):
-    _check(load().dr_solve_device(h, F_device_ptr, ids_device_ptr, int(n_ids), int(start)))
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_solve_device(h, F_device_ptr, _ptr(idsa), int(n_ids), int(start)))
+
+
+def dr_advance(h: int, F: np.ndarray, ids: np.ndarray, starts: np.ndarray, budget: int):
+    ids = np.ascontiguousarray(ids, np.int32)
+    F = np.ascontiguousarray(F, np.float64).reshape(len(ids), 9)
+    starts = np.ascontiguousarray(starts, np.int32)
+    _check(load().dr_advance(h, _ptr(F), _ptr(ids), _ptr(starts), len(ids), int(budget)))
+
+
+def dr_results(h: int, ids: np.ndarray) -> dict:
+    ids = np.ascontiguousarray(ids, np.int32)
+    n = len(ids)
+    sig = np.zeros((n, 9)); sigf = np.zeros((n, 9))
+    res = np.zeros(n, np.int32); it = np.zeros(n, np.int64)
+    rho = np.zeros(n); ke = np.zeros(n)
+    _check(load().dr_results(h, _ptr(ids), n, _ptr(sig), _ptr(sigf), _ptr(res), _ptr(it),
+                             _ptr(rho), _ptr(ke)))
+    return dict(sigma=sig.reshape(n, 3, 3), sigma_fib=sigf.reshape(n, 3, 3), result=res,
+                iters=it, rho=rho, ke=ke)
 
 
 def dr_solve_loop(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int = DR_START_AFFINE):
@@ -220,12 +246,14 @@ class DRBatch:
     """Owns one dr_batch handle for a paper_2305_07030_amd.inputs.Batch."""
 
     def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
-                 block=0, placement=DR_PLACE_AUTO, precision=DR_FP64, stream=None):
+                 block=0, placement=DR_PLACE_AUTO, chunk=0, stall_window=0, precision=DR_FP64,
+                 stream=None):
         self.batch = batch
         self.P = len(batch)
         self.total_nodes = batch.total_nodes
         self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
-                                dt_safety=dt_safety, block=block, placement=placement)
+                                dt_safety=dt_safety, block=block, placement=placement,
+                                chunk=chunk, stall_window=stall_window)
         self.h = dr_batch_create(batch.packed(), self.opt, stream if stream is not None else current_stream())
         self._n_last = None
 
@@ -243,10 +271,19 @@ class DRBatch:
         dr_solve_loop(self.h, F, ids, start)
         self._n_last = F.shape[0]
 
-    def solve_device(self, F_dev, ids_dev=None, start=DR_START_AFFINE):
+    def solve_device(self, F_dev, ids=None, start=DR_START_AFFINE):
         n = int(F_dev.shape[0])
-        dr_solve_device(self.h, F_dev.data_ptr(), None if ids_dev is None else ids_dev.data_ptr(), n, start)
+        dr_solve_device(self.h, F_dev.data_ptr(), ids, n, start)
         self._n_last = n
+
+    def advance(self, ids, starts, budget, F=None):
+        ids = np.asarray(ids, np.int32)
+        if F is None:
+            F = np.tile(np.eye(3), (len(ids), 1, 1))
+        dr_advance(self.h, F, ids, starts, budget)
+
+    def query(self, ids) -> dict:
+        return dr_results(self.h, ids)
 
     def results(self, want_u=False) -> dict:
         if self._n_last is None:
