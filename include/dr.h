@@ -258,6 +258,47 @@ dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_n
  */
 dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor);
 
+/*
+ * Size classes.  A batch splits its problems by node count into classes; each
+ * class has one launch shape (threads per workgroup, nodes per thread, gather
+ * chunk, placement) used for every solve of the batch, and the classes of a
+ * launch run concurrently on internal streams.  By default: the largest set
+ * of problems the LDS / register variant can hold, then the rest in global
+ * placement.  A problem's result depends only on its class's shape, not on
+ * which other problems share a launch.
+ *
+ * dr_batch_class_info: class c in [0, *n_classes); any output may be NULL.
+ *   n_lo, n_hi       node counts covered (inclusive)
+ *   n_problems       problems of the batch in the class
+ *   block, nodes_per_thread (0 = global placement), chunk, lds_bytes
+ */
+dr_status dr_batch_class_info(const dr_batch *b, int32_t c, int32_t *n_classes, int32_t *n_lo,
+                              int32_t *n_hi, int32_t *n_problems, int32_t *block,
+                              int32_t *nodes_per_thread, int32_t *chunk, int32_t *lds_bytes);
+
+/*
+ * Replaces the size classes (the autotuner's entry point): class k covers the
+ * node counts (n_hi[k-1], n_hi[k]] with the given block (0/256/512/1024),
+ * chunk (0/2/4) and placement (dr_placement); problems above n_hi[n-1] get the
+ * automatic split.  n_hi must increase.  Only before the first solve of the
+ * batch (DR_E_STATE afterwards); DR_E_INVALID when a DR_PLACE_LDS class
+ * cannot hold its largest problem.
+ */
+dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi,
+                             const int32_t *block, const int32_t *chunk, const int32_t *placement);
+
+/*
+ * Captures one solve step (as dr_solve_device with these arguments: F_device
+ * [n_ids * 9] in device memory, host ids or NULL for all, start mode) into a
+ * HIP graph held by the batch, replacing any earlier capture; dr_graph_launch
+ * replays it on the batch stream (re-staging the slot lists first).  The
+ * batch must have been created on a non-default stream (DR_E_STATE).  The
+ * results of a replay are read with dr_stress as after dr_solve.
+ */
+dr_status dr_graph_capture(dr_batch *b, const double *F_device, const int32_t *ids, int32_t n_ids,
+                           int32_t start);
+dr_status dr_graph_launch(dr_batch *b);
+
 /* Releases the handle and its device memory (waits for its stream first).
  * NULL is ignored. */
 void dr_batch_destroy(dr_batch *b);

@@ -100,10 +100,29 @@ struct dr_batch {
     // last dr_solve* call
     int32_t last_n = -1;
     std::vector<int32_t> last_ids;
-    // One launch shape for every launch of the batch (fixed at creation from
-    // the largest problem), so a problem's arithmetic -- and its result, bit
-    // for bit -- does not depend on which other problems share the launch.
-    LaunchPlan plan{0, 0, 0, 4, 0};
+    // Size classes: each class has one launch shape, fixed before the first
+    // solve, so a problem's arithmetic -- and its result, bit for bit --
+    // depends only on its size class, not on which problems share a launch.
+    // Classes are launched concurrently on their own streams (fork / join on
+    // the batch stream).
+    struct Class {
+        int32_t n_lo = 0, n_hi = 0; // node counts covered (inclusive)
+        int32_t n_max = 0;          // largest problem of the batch in the class
+        int32_t count = 0;          // problems of the batch in the class
+        LaunchPlan plan{0, 0, 0, 4, 0};
+        hipStream_t st = nullptr;
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Class> classes;
+    std::vector<int8_t> class_of;       // per problem
+    std::vector<int32_t> slot_count;    // per class, slots of the staged launch
+    std::vector<int32_t> slot_off;      // per class, first entry in the slot order
+    hipEvent_t fork = nullptr;
+    bool solved_once = false;
+    // captured solve step
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int32_t> graph_ids;
 };
 
 namespace {
@@ -121,6 +140,13 @@ void free_all(dr_batch *b)
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto &c : b->classes) {
+        if (c.done) (void)hipEventDestroy(c.done);
+        if (c.st) (void)hipStreamDestroy(c.st);
+    }
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
 }
 
 // 30-bit Morton key of a point in the unit cube (clamped).
@@ -472,6 +498,113 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     return pl;
 }
 
+// One requested class plan (dr_set_class_plan).
+struct ClassRequest {
+    int32_t n_hi;
+    int32_t block, chunk, placement;
+};
+
+// Splits the problems into size classes and gives each its launch shape.
+// Requested classes (ascending n_hi) come first; the problems above the last
+// requested bound get the automatic split: the largest set that fits the
+// LDS / register variant, then the rest in global placement.
+dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
+{
+    std::vector<dr_batch::Class> cls;
+    int32_t lo = 1;
+    auto n_max_in = [&](int32_t a, int32_t z) {
+        int32_t m = 0, c = 0;
+        for (const auto &h : b->hp)
+            if (h.N >= a && h.N <= z) { m = std::max(m, h.N); ++c; }
+        return std::make_pair(m, c);
+    };
+    for (const auto &r : req) {
+        dr_batch::Class c;
+        c.n_lo = lo;
+        c.n_hi = r.n_hi;
+        auto mc = n_max_in(lo, r.n_hi);
+        c.n_max = mc.first;
+        c.count = mc.second;
+        dr_options o = b->opt;
+        o.block = r.block;
+        o.chunk = r.chunk;
+        o.placement = r.placement;
+        c.plan = plan_for(o, std::max(c.n_max, 1));
+        if (c.plan.npt < 0)
+            return fail(DR_E_INVALID, "class up to %d nodes: DR_PLACE_LDS cannot hold %d nodes",
+                        r.n_hi, c.n_max);
+        cls.push_back(c);
+        lo = r.n_hi + 1;
+    }
+    // automatic split of the rest
+    const int32_t top = INT32_MAX;
+    if (b->opt.placement == DR_PLACE_GLOBAL || b->opt.placement == DR_PLACE_LDS) {
+        dr_batch::Class c;
+        c.n_lo = lo;
+        c.n_hi = top;
+        auto mc = n_max_in(lo, top);
+        c.n_max = mc.first;
+        c.count = mc.second;
+        c.plan = plan_for(b->opt, std::max(c.n_max, 1));
+        if (c.plan.npt < 0)
+            return fail(DR_E_INVALID, "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
+                        c.n_max, b->opt.block);
+        cls.push_back(c);
+    } else {
+        // largest N (among the remaining problems) that the register variant holds
+        int32_t fit = 0;
+        for (const auto &h : b->hp)
+            if (h.N >= lo && h.N > fit && plan_for(b->opt, h.N).npt > 0) fit = h.N;
+        if (fit >= lo) {
+            dr_batch::Class c;
+            c.n_lo = lo;
+            c.n_hi = fit;
+            auto mc = n_max_in(lo, fit);
+            c.n_max = mc.first;
+            c.count = mc.second;
+            c.plan = plan_for(b->opt, c.n_max);
+            cls.push_back(c);
+            lo = fit + 1;
+        }
+        dr_batch::Class g;
+        g.n_lo = lo;
+        g.n_hi = top;
+        auto mc = n_max_in(lo, top);
+        g.n_max = mc.first;
+        g.count = mc.second;
+        dr_options o = b->opt;
+        o.placement = DR_PLACE_GLOBAL;
+        g.plan = plan_for(o, std::max(g.n_max, 1));
+        cls.push_back(g);
+    }
+    // keep the streams of the old classes for reuse
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> ev;
+    for (auto &c : b->classes) { st.push_back(c.st); ev.push_back(c.done); }
+    for (size_t k = 0; k < cls.size(); ++k) {
+        if (k < st.size()) { cls[k].st = st[k]; cls[k].done = ev[k]; }
+        else {
+            HIPCHECK(hipStreamCreateWithFlags(&cls[k].st, hipStreamNonBlocking));
+            HIPCHECK(hipEventCreateWithFlags(&cls[k].done, hipEventDisableTiming));
+        }
+    }
+    for (size_t k = cls.size(); k < st.size(); ++k) {
+        (void)hipEventDestroy(ev[k]);
+        (void)hipStreamDestroy(st[k]);
+    }
+    b->classes = cls;
+    b->class_of.assign(b->P, 0);
+    for (int32_t p = 0; p < b->P; ++p)
+        for (size_t k = 0; k < cls.size(); ++k)
+            if (b->hp[p].N >= cls[k].n_lo && b->hp[p].N <= cls[k].n_hi) {
+                b->class_of[p] = (int8_t)k;
+                break;
+            }
+    b->slot_count.assign(cls.size(), 0);
+    b->slot_off.assign(cls.size(), 0);
+    return DR_OK;
+}
+
 SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
 {
     SolveArgs a{};
@@ -564,9 +697,18 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
         b->h_order[k] = k;
         if (starts) b->h_starts[k] = starts[k];
     }
+    // slots grouped by size class, largest problem first within a class
     std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
+        const int cs = b->class_of[b->h_ids[s]], ct = b->class_of[b->h_ids[t]];
+        if (cs != ct) return cs < ct;
         return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
     });
+    std::fill(b->slot_count.begin(), b->slot_count.end(), 0);
+    for (int32_t k = 0; k < n_ids; ++k) ++b->slot_count[b->class_of[b->h_ids[k]]];
+    for (size_t c = 0, off = 0; c < b->classes.size(); ++c) {
+        b->slot_off[c] = (int32_t)off;
+        off += b->slot_count[c];
+    }
     if (F)
         HIPCHECK(hipMemcpyAsync(b->d_F, b->h_F, 9 * sizeof(double) * (size_t)n_ids,
                                 hipMemcpyHostToDevice, b->stream));
@@ -612,10 +754,33 @@ dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sig
     return DR_OK;
 }
 
+// Launches the staged slots: one DR + stress launch per size class with
+// slots, concurrently on the class streams (fork / join on the batch stream).
 dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
 {
-    const int rc = drk::launch_solve(a, b->plan, b->stream);
-    if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+    int used = 0, only = -1;
+    for (size_t c = 0; c < b->classes.size(); ++c)
+        if (b->slot_count[c] > 0) { ++used; only = (int)c; }
+    auto one = [&](size_t c, hipStream_t st) -> dr_status {
+        SolveArgs ac = a;
+        ac.order = a.order + b->slot_off[c];
+        ac.n_solve = b->slot_count[c];
+        const int rc = drk::launch_solve(ac, b->classes[c].plan, st);
+        if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
+        return DR_OK;
+    };
+    b->solved_once = true;
+    if (used == 1) return one((size_t)only, b->stream);
+    HIPCHECK(hipEventRecord(b->fork, b->stream));
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+        if (b->slot_count[c] == 0) continue;
+        HIPCHECK(hipStreamWaitEvent(b->classes[c].st, b->fork, 0));
+        dr_status s = one(c, b->classes[c].st);
+        if (s != DR_OK) return s;
+        HIPCHECK(hipEventRecord(b->classes[c].done, b->classes[c].st));
+    }
+    for (size_t c = 0; c < b->classes.size(); ++c)
+        if (b->slot_count[c] > 0) HIPCHECK(hipStreamWaitEvent(b->stream, b->classes[c].done, 0));
     return DR_OK;
 }
 
@@ -664,16 +829,20 @@ dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt, void *
         b->total_slices = (int64_t)pk.slice_w.size();
         b->total_inc = (int64_t)pk.nbr.size();
         b->n_max = pk.n_max;
-        b->plan = plan_for(*opt, pk.n_max);
         b->desc = pk.desc;
         b->running.assign(b->P, 0);
+        b->hp = std::move(pk.hp);
         s = create_device(b, pk);
+        if (s == DR_OK) s = build_classes(b, {});
+        if (s == DR_OK) {
+            hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+            if (e != hipSuccess) s = fail(DR_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        }
         if (s != DR_OK) {
             free_all(b);
             delete b;
             return s;
         }
-        b->hp = std::move(pk.hp);
         *out = b;
         return DR_OK;
     } catch (const std::bad_alloc &) {
@@ -885,14 +1054,121 @@ dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_n
 {
     g_err.clear();
     if (!b) return fail(DR_E_INVALID, "batch is NULL");
-    const LaunchPlan &pl = b->plan;
+    // the class holding the largest problem
+    const LaunchPlan &pl = b->classes[b->class_of[0]].plan;
+    size_t big = 0;
+    for (int32_t p = 0; p < b->P; ++p)
+        if (b->hp[p].N == b->n_max) { big = (size_t)b->class_of[p]; break; }
+    const LaunchPlan &pb = b->classes[big].plan;
+    (void)pl;
     if (n_problems) *n_problems = b->P;
     if (total_nodes) *total_nodes = b->total_nodes;
     if (total_fibers) *total_fibers = b->total_fibers;
-    if (block) *block = pl.block;
-    if (lds_bytes) *lds_bytes = pl.lds_bytes;
-    if (nodes_per_thread) *nodes_per_thread = pl.npt;
+    if (block) *block = pb.block;
+    if (lds_bytes) *lds_bytes = pb.lds_bytes;
+    if (nodes_per_thread) *nodes_per_thread = pb.npt;
     return DR_OK;
+}
+
+dr_status dr_batch_class_info(const dr_batch *b, int32_t c, int32_t *n_classes, int32_t *n_lo,
+                              int32_t *n_hi, int32_t *n_problems, int32_t *block,
+                              int32_t *nodes_per_thread, int32_t *chunk, int32_t *lds_bytes)
+{
+    g_err.clear();
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    if (n_classes) *n_classes = (int32_t)b->classes.size();
+    if (c < 0 || c >= (int32_t)b->classes.size())
+        return fail(DR_E_INVALID, "class %d out of range (%d classes)", c, (int)b->classes.size());
+    const auto &k = b->classes[c];
+    if (n_lo) *n_lo = k.n_lo;
+    if (n_hi) *n_hi = k.n_hi;
+    if (n_problems) *n_problems = k.count;
+    if (block) *block = k.plan.block;
+    if (nodes_per_thread) *nodes_per_thread = k.plan.npt;
+    if (chunk) *chunk = k.plan.chunk;
+    if (lds_bytes) *lds_bytes = k.plan.lds_bytes;
+    return DR_OK;
+}
+
+dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi,
+                             const int32_t *block, const int32_t *chunk, const int32_t *placement)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (b->solved_once)
+            return fail(DR_E_STATE, "class plans must be set before the first solve of the batch");
+        if (n_classes < 0 || n_classes > 16) return fail(DR_E_INVALID, "n_classes must be in [0, 16]");
+        if (n_classes > 0 && (!n_hi || !block || !chunk || !placement))
+            return fail(DR_E_INVALID, "a class-plan array is NULL");
+        std::vector<ClassRequest> req;
+        for (int32_t k = 0; k < n_classes; ++k) {
+            if (k > 0 && n_hi[k] <= n_hi[k - 1])
+                return fail(DR_E_INVALID, "n_hi must increase (class %d)", k);
+            if (n_hi[k] < 1) return fail(DR_E_INVALID, "n_hi of class %d must be >= 1", k);
+            if (block[k] != 0 && block[k] != 256 && block[k] != 512 && block[k] != 1024)
+                return fail(DR_E_INVALID, "block of class %d must be 0, 256, 512 or 1024", k);
+            if (chunk[k] != 0 && chunk[k] != 2 && chunk[k] != 4)
+                return fail(DR_E_INVALID, "chunk of class %d must be 0, 2 or 4", k);
+            if (placement[k] < DR_PLACE_AUTO || placement[k] > DR_PLACE_GLOBAL)
+                return fail(DR_E_INVALID, "placement of class %d is not a dr_placement value", k);
+            req.push_back(ClassRequest{n_hi[k], block[k], chunk[k], placement[k]});
+        }
+        return build_classes(b, req);
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_set_class_plans");
+    }
+}
+
+dr_status dr_graph_capture(dr_batch *b, const double *F_device, const int32_t *ids, int32_t n_ids,
+                           int32_t start)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!F_device) return fail(DR_E_INVALID, "F_device is NULL");
+        if (!b->stream)
+            return fail(DR_E_STATE, "graph capture needs a batch created on a non-default stream");
+        dr_status s = check_start(start, false);
+        if (s != DR_OK) return s;
+        if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
+        if ((s = stage(b, nullptr, ids, nullptr, n_ids)) != DR_OK) return s;
+        HIPCHECK(hipStreamSynchronize(b->stream));
+        if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
+        a.F = F_device;
+        HIPCHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        s = launch_or_fail(b, a);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (s != DR_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+        if (e != hipSuccess) return fail(DR_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIPCHECK(hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+        b->graph_ids = b->last_ids;
+        return DR_OK;
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_graph_capture");
+    }
+}
+
+dr_status dr_graph_launch(dr_batch *b)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!b->graph_exec) return fail(DR_E_STATE, "no captured solve (dr_graph_capture)");
+        // the slot arrays the graph's kernels read are re-staged first
+        dr_status s = stage(b, nullptr, b->graph_ids.data(), nullptr, (int32_t)b->graph_ids.size());
+        if (s != DR_OK) return s;
+        HIPCHECK(hipGraphLaunch(b->graph_exec, b->stream));
+        for (int32_t p : b->graph_ids) b->running[p] = 0;
+        b->last_n = (int32_t)b->graph_ids.size();
+        return DR_OK;
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_graph_launch");
+    }
 }
 
 dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor)

@@ -775,7 +775,7 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
     __shared__ double red[(kStressBlock / kWave) * kRedStride];
     constexpr int NW = kStressBlock / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int slot = slot0 + (int)blockIdx.x;
+    const int slot = A.order ? A.order[slot0 + (int)blockIdx.x] : slot0 + (int)blockIdx.x;
     const int p = A.ids ? A.ids[slot] : slot;
     const int st = A.status[p];
     if (st == kStatusRunning || st == kStatusIdle) return; // uniform over the workgroup

@@ -26,7 +26,8 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 # Every exported symbol of include/dr.h.
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
            "dr_stress", "dr_advance", "dr_results", "dr_sync", "dr_solve_loop", "dr_batch_info",
-           "dr_batch_scalars", "dr_batch_destroy", "dr_last_error")
+           "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
+           "dr_graph_launch", "dr_batch_destroy", "dr_last_error")
 
 
 class DrError(RuntimeError):
@@ -96,6 +97,14 @@ def load():
     lib.dr_batch_info.restype = C.c_int
     lib.dr_batch_scalars.argtypes = [vp, vp, vp, vp]
     lib.dr_batch_scalars.restype = C.c_int
+    lib.dr_batch_class_info.argtypes = [vp, C.c_int32] + [vp] * 8
+    lib.dr_batch_class_info.restype = C.c_int
+    lib.dr_set_class_plans.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    lib.dr_set_class_plans.restype = C.c_int
+    lib.dr_graph_capture.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_graph_capture.restype = C.c_int
+    lib.dr_graph_launch.argtypes = [vp]
+    lib.dr_graph_launch.restype = C.c_int
     lib.dr_batch_destroy.argtypes = [vp]
     lib.dr_batch_destroy.restype = None
     lib.dr_last_error.argtypes = []
@@ -223,6 +232,37 @@ def dr_batch_scalars(h: int, n_problems: int) -> dict:
     return dict(dt=dt, c=c, s_floor=fl)
 
 
+def dr_batch_class_info(h: int) -> list:
+    """One dict per size class."""
+    out = []
+    c = 0
+    while True:
+        v = [C.c_int32() for _ in range(8)]
+        rc = load().dr_batch_class_info(h, c, *[C.addressof(x) for x in v])
+        if c >= v[0].value:
+            break
+        _check(rc)
+        out.append(dict(n_lo=v[1].value, n_hi=v[2].value, n_problems=v[3].value, block=v[4].value,
+                        nodes_per_thread=v[5].value, chunk=v[6].value, lds_bytes=v[7].value))
+        c += 1
+    return out
+
+
+def dr_set_class_plans(h: int, n_hi, block, chunk, placement):
+    a = [np.ascontiguousarray(x, np.int32) for x in (n_hi, block, chunk, placement)]
+    _check(load().dr_set_class_plans(h, len(a[0]), *[_ptr(x) for x in a]))
+
+
+def dr_graph_capture(h: int, F_device_ptr: int, ids: Optional[np.ndarray], n_ids: int,
+                     start: int = DR_START_AFFINE):
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_graph_capture(h, F_device_ptr, _ptr(idsa), int(n_ids), int(start)))
+
+
+def dr_graph_launch(h: int):
+    _check(load().dr_graph_launch(h))
+
+
 def dr_batch_destroy(h: int):
     load().dr_batch_destroy(h)
 
@@ -299,6 +339,23 @@ class DRBatch:
 
     def info(self) -> dict:
         return dr_batch_info(self.h)
+
+    def classes(self) -> list:
+        return dr_batch_class_info(self.h)
+
+    def set_class_plans(self, plans):
+        """plans: list of dicts with n_hi, block, chunk, placement."""
+        dr_set_class_plans(self.h, [p["n_hi"] for p in plans], [p["block"] for p in plans],
+                           [p["chunk"] for p in plans], [p["placement"] for p in plans])
+
+    def graph_capture(self, F_dev, ids=None, start=DR_START_AFFINE):
+        n = int(F_dev.shape[0])
+        dr_graph_capture(self.h, F_dev.data_ptr(), ids, n, start)
+        self._graph_n = n
+
+    def graph_launch(self):
+        dr_graph_launch(self.h)
+        self._n_last = self._graph_n
 
     def scalars(self) -> dict:
         return dr_batch_scalars(self.h, self.P)

@@ -1,0 +1,121 @@
+"""Size classes (several launch shapes in one batch, run concurrently) and the
+HIP-graph captured solve step, through the C ABI."""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_07030_amd import dr
+from paper_2305_07030_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+S = 0.9
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dr.load()
+    O.build(force=False)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def mixed_batch():
+    rng = np.random.default_rng(61)
+    nets = [I.draw_network(rng, n) for n in (300, 1200, 7100, 450, 8000)]
+    F = np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets])
+    return I.Batch(nets, F)
+
+
+def oracle_fixed(batch, K, beta):
+    """Oracle state after K passes, and how far it moves when its start is
+    perturbed by 1e-15 (round-off amplification of the floppy transient):
+    list of (result, max |du|, relative sigma change)."""
+    def one(i):
+        net, F = batch.nets[i], batch.F[i]
+        a = O.solve(net, F, tol=1e-30, max_iter=K, beta=beta, dt_safety=S)
+        u0 = net.X @ (F - np.eye(3)).T
+        u0 = u0 + np.random.default_rng(1).normal(size=u0.shape) * 1e-15 * (net.fixed == 0)[:, None]
+        b = O.solve(net, F, tol=1e-30, max_iter=K, beta=beta, dt_safety=S, start=O.START_WARM,
+                    F_prev=F, u_prev=u0)
+        return a, np.abs(a.u - b.u).max(), rel(b.sigma, a.sigma)
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(len(batch))))
+
+
+def test_automatic_classes_split_and_match_oracle():
+    batch = mixed_batch()
+    K = 300
+    b = dr.DRBatch(batch, tol=1e-30, max_iter=K, damping=1e-3, dt_safety=S)
+    cls = b.classes()
+    say("classes", cls)
+    assert len(cls) == 2 and cls[0]["nodes_per_thread"] > 0 and cls[1]["nodes_per_thread"] == 0
+    assert cls[0]["n_problems"] == 3 and cls[1]["n_problems"] == 2
+    b.solve()
+    g = b.results(want_u=True)
+    o = oracle_fixed(batch, K, 1e-3)
+    for i, (oi, su, ss) in enumerate(o):
+        err = np.abs(g["u_list"][i] - oi.u).max()
+        say(f"net {i} N={batch.nets[i].n_nodes}: |du| {err:.2e} (sensitivity {su:.2e}), "
+            f"sigma rel {rel(g['sigma'][i], oi.sigma):.2e} (sensitivity {ss:.2e})")
+        assert g["iters"][i] == K == oi.iters
+        assert err < 1e-12 + 100 * su
+        assert rel(g["sigma"][i], oi.sigma) < 1e-12 + 100 * ss
+
+
+def test_class_plan_override():
+    batch = mixed_batch()
+    K = 300
+    b = dr.DRBatch(batch, tol=1e-30, max_iter=K, damping=1e-3, dt_safety=S)
+    b.set_class_plans([dict(n_hi=500, block=256, chunk=4, placement=dr.DR_PLACE_LDS),
+                       dict(n_hi=1500, block=512, chunk=2, placement=dr.DR_PLACE_LDS)])
+    cls = b.classes()
+    say("override classes", cls)
+    assert [c["n_problems"] for c in cls] == [2, 1, 2]
+    assert cls[0]["block"] == 256 and cls[1]["block"] == 512 and cls[1]["chunk"] == 2
+    b.solve()
+    g = b.results()
+    o = oracle_fixed(batch, K, 1e-3)
+    for i, (oi, su, ss) in enumerate(o):
+        assert rel(g["sigma"][i], oi.sigma) < 1e-12 + 100 * ss
+    with pytest.raises(dr.DrError):
+        b.set_class_plans([dict(n_hi=500, block=256, chunk=4, placement=dr.DR_PLACE_LDS)])
+
+
+def test_graph_replay_equals_eager():
+    import torch
+    batch = I.small_batch(8, 100, 900, 0.02, seed=62)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S, stream=st.cuda_stream)
+        Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+        b.solve_device(Fd)
+        eager = b.results()
+        b.graph_capture(Fd)
+        for k in range(3):
+            # eager work of the program between replays
+            x = torch.randn(1000, device="cuda").sum()
+            torch.cuda.synchronize()
+            b.graph_launch()
+            g = b.results()
+            say(f"replay {k}: passes {list(g['iters'])}")
+            assert np.array_equal(g["sigma"], eager["sigma"])
+            assert np.array_equal(g["iters"], eager["iters"])
+            assert (g["result"] == dr.DR_CONVERGED).all()
+        # an eager solve after the replays is unchanged too
+        b.solve_device(Fd)
+        assert np.array_equal(b.results()["sigma"], eager["sigma"])
+    torch.cuda.synchronize()
