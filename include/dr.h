@@ -265,7 +265,8 @@ dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_f
  * launch run concurrently on internal streams.  By default: the largest set
  * of problems the LDS / register variant can hold, then the rest in global
  * placement.  A problem's result depends only on its class's shape, not on
- * which other problems share a launch.
+ * which other problems share a launch.  Classes that would hold no problem
+ * of the batch are dropped, so every listed class has n_problems > 0.
  *
  * dr_batch_class_info: class c in [0, *n_classes); any output may be NULL.
  *   n_lo, n_hi       node counts covered (inclusive)

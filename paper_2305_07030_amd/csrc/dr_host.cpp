@@ -577,6 +577,11 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         g.plan = plan_for(o, std::max(g.n_max, 1));
         cls.push_back(g);
     }
+    // classes without problems launch nothing: drop them (at least one stays)
+    std::vector<dr_batch::Class> kept;
+    for (const auto &c : cls)
+        if (c.count > 0) kept.push_back(c);
+    if (!kept.empty()) cls.swap(kept);
     // keep the streams of the old classes for reuse
     std::vector<hipStream_t> st;
     std::vector<hipEvent_t> ev;

@@ -119,3 +119,28 @@ def test_graph_replay_equals_eager():
         b.solve_device(Fd)
         assert np.array_equal(b.results()["sigma"], eager["sigma"])
     torch.cuda.synchronize()
+
+
+def test_tuned_plans_apply_and_match_oracle(tmp_path):
+    from paper_2305_07030_amd import tune as T
+    rng = np.random.default_rng(63)
+    sizes = [120, 200, 350, 480, 700, 900, 1500, 2600]
+    nets = [I.draw_network(rng, n) for n in sizes]
+    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
+    tu = T.Tuner(edges=(256, 1024), passes=200, sample_size=4, reps=1,
+                 cache_path=str(tmp_path / "tune.json"), log=say)
+    plans = tu.tune(batch)
+    say("tuned", [{k: p[k] for k in ("n_hi", "block", "chunk", "placement")} for p in plans])
+    assert [p["n_hi"] for p in plans] == [256, 1024, 2600]
+    b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
+    T.apply(b, plans)
+    assert [c["n_problems"] for c in b.classes()] == [2, 4, 2]
+    b.solve()
+    g = b.results()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        os_ = list(ex.map(lambda i: O.solve(batch.nets[i], batch.F[i], tol=1e-8, beta=1e-3, dt_safety=S),
+                          range(len(batch))))
+    for i, o in enumerate(os_):
+        assert g["result"][i] == dr.DR_CONVERGED and o.status == O.CONVERGED
+        assert abs(int(g["iters"][i]) - o.iters) <= 1 + 2e-3 * o.iters
+        assert rel(g["sigma"][i], o.sigma) < 1e-8
