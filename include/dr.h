@@ -97,8 +97,9 @@ typedef enum {
  *   fiber_nodes         [total_fibers * 2] problem-local node ids (a, b), a != b
  *   EA                  [total_fibers] finite and > 0
  *   fixed               [total_nodes] 1 = prescribed node, 0 = free
- * Each problem needs >= 1 node, every free node needs >= 1 fiber and every
- * fiber a nonzero reference length.
+ * Each problem needs 1 .. 524288 nodes (the global-placement kernel keeps a
+ * problem's 64-node slice headers in LDS), every free node needs >= 1 fiber
+ * and every fiber a nonzero reference length.
  */
 typedef struct {
     int32_t n_problems;
@@ -122,9 +123,10 @@ typedef struct {
  *   placement   a dr_placement value; DR_PLACE_LDS is rejected at creation
  *               when the largest problem does not fit (3 * 8 B per node of
  *               LDS, at most 8 nodes per thread)
- *   chunk       incidences whose loads the force gather issues together:
- *               0 = automatic, else 2 or 4 (a tuning knob; results do not
- *               depend on it)
+ *   chunk       incidences per step of the force gather, whose loads are
+ *               issued one step ahead: 0 = automatic, else 1, 2 or 4 (a
+ *               tuning knob; results do not depend on it; global placement
+ *               with 256 threads always uses 1)
  *   stall_window  >= 0; 0 = off.  Otherwise a solve also ends (DR_STALLED)
  *               when its best residual has not improved by 0.1 % during the
  *               last stall_window passes.  Not part of the paper's loop: a
@@ -280,7 +282,7 @@ dr_status dr_batch_class_info(const dr_batch *b, int32_t c, int32_t *n_classes, 
 /*
  * Replaces the size classes (the autotuner's entry point): class k covers the
  * node counts (n_hi[k-1], n_hi[k]] with the given block (0/256/512/1024),
- * chunk (0/2/4) and placement (dr_placement); problems above n_hi[n-1] get the
+ * chunk (0/1/2/4) and placement (dr_placement); problems above n_hi[n-1] get the
  * automatic split.  n_hi must increase.  Only before the first solve of the
  * batch (DR_E_STATE afterwards); DR_E_INVALID when a DR_PLACE_LDS class
  * cannot hold its largest problem.

@@ -180,8 +180,8 @@ dr_status validate_options(const dr_options *o)
         return fail(DR_E_INVALID, "block must be 0, 256, 512 or 1024 (got %d)", o->block);
     if (o->placement < DR_PLACE_AUTO || o->placement > DR_PLACE_GLOBAL)
         return fail(DR_E_INVALID, "placement %d is not a dr_placement value", o->placement);
-    if (o->chunk != 0 && o->chunk != 2 && o->chunk != 4)
-        return fail(DR_E_INVALID, "chunk must be 0, 2 or 4 (got %d)", o->chunk);
+    if (o->chunk != 0 && o->chunk != 1 && o->chunk != 2 && o->chunk != 4)
+        return fail(DR_E_INVALID, "chunk must be 0, 1, 2 or 4 (got %d)", o->chunk);
     if (o->stall_window < 0) return fail(DR_E_INVALID, "stall_window must be >= 0");
     return DR_OK;
 }
@@ -212,8 +212,9 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
     for (int32_t p = 0; p < P; ++p) {
         if (no[p + 1] - no[p] < 1)
             return fail(DR_E_INVALID, "problem %d has no nodes", p);
-        if (no[p + 1] - no[p] > (int64_t)INT32_MAX / 4)
-            return fail(DR_E_INVALID, "problem %d has too many nodes", p);
+        if (no[p + 1] - no[p] > (int64_t)drk::kWave * drk::kGlbHdrMax)
+            return fail(DR_E_INVALID, "problem %d has %lld nodes (at most %d per problem)", p,
+                        (long long)(no[p + 1] - no[p]), drk::kWave * drk::kGlbHdrMax);
         if (fo[p + 1] < fo[p]) return fail(DR_E_INVALID, "fiber_offsets decrease at problem %d", p);
     }
     if (fo[P] > 0 && !nets->fiber_nodes) return fail(DR_E_INVALID, "fiber_nodes is NULL");
@@ -484,8 +485,9 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
         return pl;
     }
     if (fits && opt.placement != DR_PLACE_GLOBAL) {
-        // chunks of 2 keep the 1024-thread FP64 variants within 128 VGPRs
-        pl.chunk = opt.chunk ? opt.chunk : ((blk == 1024 && !pl.fp32) ? 2 : 4);
+        // at 1024 threads (128 VGPRs) the prefetched chunk shrinks with the
+        // nodes held per thread: 2 up to 4 nodes, then 1
+        pl.chunk = opt.chunk ? opt.chunk : (blk == 1024 ? (npt <= 4 ? 2 : 1) : 4);
         pl.block = blk;
         pl.npt = npt < 1 ? 1 : npt;
         pl.lds_bytes = reg_lds(blk, n_max);
@@ -493,8 +495,11 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     }
     pl.block = block ? block : 1024;
     pl.npt = 0;
-    pl.chunk = 4;
-    pl.lds_bytes = (pl.block / drk::kWave) * 20 * 8;
+    // 256 threads: chunks of 1 only (the only global build of that width)
+    pl.chunk = pl.block == 256 ? 1 : (opt.chunk ? opt.chunk : (pl.block == 1024 ? 1 : 2));
+    // reduction area plus the slice-header table (16 B per slice)
+    const int slices = (n_max + drk::kWave - 1) / drk::kWave; // <= kGlbHdrMax (validated)
+    pl.lds_bytes = (pl.block / drk::kWave) * 20 * 8 + 16 * slices;
     return pl;
 }
 
@@ -1113,8 +1118,8 @@ dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi
             if (n_hi[k] < 1) return fail(DR_E_INVALID, "n_hi of class %d must be >= 1", k);
             if (block[k] != 0 && block[k] != 256 && block[k] != 512 && block[k] != 1024)
                 return fail(DR_E_INVALID, "block of class %d must be 0, 256, 512 or 1024", k);
-            if (chunk[k] != 0 && chunk[k] != 2 && chunk[k] != 4)
-                return fail(DR_E_INVALID, "chunk of class %d must be 0, 2 or 4", k);
+            if (chunk[k] != 0 && chunk[k] != 1 && chunk[k] != 2 && chunk[k] != 4)
+                return fail(DR_E_INVALID, "chunk of class %d must be 0, 1, 2 or 4", k);
             if (placement[k] < DR_PLACE_AUTO || placement[k] > DR_PLACE_GLOBAL)
                 return fail(DR_E_INVALID, "placement of class %d is not a dr_placement value", k);
             req.push_back(ClassRequest{n_hi[k], block[k], chunk[k], placement[k]});

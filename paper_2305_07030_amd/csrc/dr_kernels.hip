@@ -9,8 +9,9 @@
 //      incidences (deterministic node -> fiber gather, no atomics)
 //   4. forms the damped acceleration, the full-step and next half-step
 //      velocities, and its share of |g_free|^2, |g_B|^2 and 2 KE (FP64)
-//   5. wavefront reduction -> LDS -> every thread sums the wave partials in
-//      the same fixed order, so the stop decision is uniform.
+//   5. wavefront reduction -> LDS -> every wave reduces the wave partials
+//      in the same fixed order and takes lane 0's totals, so the stop
+//      decision is uniform.
 // A launch makes at most `budget` passes per problem.  A solve that is still
 // running when the budget is spent saves its state (exactly) to HBM and a
 // later launch resumes it, so a solve split over several launches gives the
@@ -38,12 +39,13 @@ enum { kConverged = 0, kMaxIter = 1, kNonFinite = 2 };
 
 // Progress of a running solve for the optional stall guard.
 struct Progress {
-    double best;  // best residual so far
+    double best;   // best squared residual ratio rho^2 so far
     int64_t nbest; // pass at which it was reached
 };
 enum { kStartAffine = 0, kStartZero = 1, kStartWarm = 2 };
 
-// Partial sums kept per wave in LDS: 3 per pass, 18 in the stress kernel.
+// Per-wave LDS record (doubles): the 3 partial sums of a pass (18 in the
+// stress kernel); in k_dr_reg doubles 4.. hold the wave's row headers.
 constexpr int kRedStride = 20;
 
 // Cross-lane move of a double with a DPP control (both 32-bit halves).
@@ -265,7 +267,7 @@ __device__ __forceinline__ void gather(const SolveArgs &A, const Aff32 &af, cons
                                        const Pos &pos, int lane, int d, T qi0, T qi1, T qi2,
                                        T &gx, T &gy, T &gz)
 {
-    static_assert(CH == 2 || CH == 4, "chunk of 2 or 4 incidences");
+    static_assert(CH == 1 || CH == 2 || CH == 4, "chunk of 1, 2 or 4 incidences");
     gx = 0; gy = 0; gz = 0;
     int64_t e = row.e0 + lane;
     int k0 = 0;
@@ -303,6 +305,110 @@ __device__ __forceinline__ void gather_stress(const SolveArgs &A, const Row &row
     for (; k0 + 2 <= row.width; k0 += 2, e += 2 * kWave)
         chunk64<2, true>(A, e, pos, k0, d, xi, yi, zi, gx, gy, gz, sf);
     if (k0 < row.width) chunk64<1, true>(A, e, pos, k0, d, xi, yi, zi, gx, gy, gz, sf);
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined gather of the register-resident kernel.  The rows of a
+// thread's NPT nodes are walked as one stream of chunks of C incidences; the
+// neighbour ids and constants of the next chunk are loaded before the current
+// chunk's positions are read and its forces formed, so the L2 latency of the
+// topology overlaps the work instead of preceding it.  Entries past a row's
+// width are clamped to its last entry (always a valid address) and masked by
+// the node's degree like the padding.
+// ---------------------------------------------------------------------------
+template <class Prec, int C> struct Pref;
+template <int C> struct Pref<P64, C> {
+    int j[C];
+    KL c[C];
+};
+template <int C> struct Pref<P32, C> {
+    int j[C];
+    KL32 c[C];
+};
+
+// Header of one slice (wave-uniform), kept in LDS for the whole solve.
+struct RowHdr {
+    int64_t e0; // first entry of the slice
+    int32_t w;  // width (0: no such slice for this wave)
+    int32_t pad;
+};
+
+template <class Prec, int C>
+__device__ __forceinline__ void pref_load(const SolveArgs &A, int64_t e0, int w, int k0, int lane,
+                                          Pref<Prec, C> &pf)
+{
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        const int k = k0 + t < w ? k0 + t : w - 1;
+        const int64_t e = e0 + (int64_t)k * kWave + lane;
+        pf.j[t] = A.nbr[e];
+        if constexpr (Prec::kDisp) pf.c[t] = A.kl32[e];
+        else pf.c[t] = A.kl[e];
+    }
+}
+
+// Forces of one chunk whose neighbour states px, py, pz are loaded (same
+// arithmetic and order as chunk64 / chunk32).
+template <int C>
+__device__ __forceinline__ void force_pre(const KL (&c)[C], const double (&px)[C],
+                                          const double (&py)[C], const double (&pz)[C],
+                                          const Aff32 &, int k0, int d, double xi, double yi,
+                                          double zi, double &gx, double &gy, double &gz)
+{
+    double dx[C], dy[C], dz[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        dx[t] = px[t] - xi; dy[t] = py[t] - yi; dz[t] = pz[t] - zi;
+    }
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        const double l2 = len2(dx[t], dy[t], dz[t]);
+        double s = c[t].k * (l2 - c[t].L2) * rsqrt(l2);
+        s = (k0 + t < d) ? s : 0.0;
+        gx += s * dx[t]; gy += s * dy[t]; gz += s * dz[t];
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void force_pre(const KL32 (&c)[C], const float (&px)[C],
+                                          const float (&py)[C], const float (&pz)[C],
+                                          const Aff32 &af, int k0, int d, float qi0, float qi1,
+                                          float qi2, float &gx, float &gy, float &gz)
+{
+    float dq0[C], dq1[C], dq2[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        dq0[t] = px[t] - qi0; dq1[t] = py[t] - qi1; dq2[t] = pz[t] - qi2;
+    }
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        const float X0 = c[t].dx, X1 = c[t].dy, X2 = c[t].dz;
+        const float f0 = af.F[0] * X0 + af.F[1] * X1 + af.F[2] * X2;
+        const float f1 = af.F[3] * X0 + af.F[4] * X1 + af.F[5] * X2;
+        const float f2 = af.F[6] * X0 + af.F[7] * X1 + af.F[8] * X2;
+        const float eaff = af.C[0] * X0 * X0 + af.C[1] * X1 * X1 + af.C[2] * X2 * X2 +
+                           af.C[3] * X0 * X1 + af.C[4] * X0 * X2 + af.C[5] * X1 * X2;
+        const float ex = eaff + 2.0f * (f0 * dq0[t] + f1 * dq1[t] + f2 * dq2[t]) +
+                         (dq0[t] * dq0[t] + dq1[t] * dq1[t] + dq2[t] * dq2[t]);
+        const float dx = f0 + dq0[t], dy = f1 + dq1[t], dz = f2 + dq2[t];
+        const float l2 = dx * dx + dy * dy + dz * dz;
+        float s = c[t].k * ex * rsqrtf(l2);
+        s = (k0 + t < d) ? s : 0.0f;
+        gx += s * dx; gy += s * dy; gz += s * dz;
+    }
+}
+
+// Forces of one prefetched chunk on a node: neighbour states from pos, then
+// force_pre.
+template <class Prec, int C, class Pos, class T = typename Prec::T>
+__device__ __forceinline__ void force_chunk(const Pref<Prec, C> &pf, const Aff32 &af,
+                                            const Pos &pos, int k0, int d, T qi0, T qi1, T qi2,
+                                            T &gx, T &gy, T &gz)
+{
+    T px[C], py[C], pz[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) pos.load(pf.j[t], px[t], py[t], pz[t]);
+    force_pre<C>(pf.c, px, py, pz, af, k0, d, qi0, qi1, qi2, gx, gy, gz);
 }
 
 // ---------------------------------------------------------------------------
@@ -389,8 +495,19 @@ __device__ __forceinline__ void write_u(const SolveArgs &A, const Slot &S, int r
     }
 }
 
-// Block-wide sums of three values; every thread returns the same totals
-// (fixed summation order over waves).
+// Lane 0's value of a double, in every lane.
+__device__ __forceinline__ double lane0(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Block-wide sums of three values; every thread returns the same totals.
+// Each wave reduces its lanes, lane 0 posts the partials; after the barrier
+// every wave reduces the NW partials over its lanes 0..NW-1 (the same inputs
+// in the same lanes, so the same rounding in every wave) and takes lane 0's
+// result, so all threads agree bit for bit.
 template <int NW>
 __device__ __forceinline__ void block_sum3(double *red, int lane, int wave, double &a, double &b,
                                            double &c)
@@ -403,37 +520,49 @@ __device__ __forceinline__ void block_sum3(double *red, int lane, int wave, doub
     }
     __syncthreads();
     double ta = 0.0, tb = 0.0, tc = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        ta += red[w * kRedStride + 0];
-        tb += red[w * kRedStride + 1];
-        tc += red[w * kRedStride + 2];
+    if (lane < NW) {
+        ta = red[lane * kRedStride + 0];
+        tb = red[lane * kRedStride + 1];
+        tc = red[lane * kRedStride + 2];
     }
-    a = ta; b = tb; c = tc;
+    a = lane0(wave_sum(ta));
+    b = lane0(wave_sum(tb));
+    c = lane0(wave_sum(tc));
 }
 
 // Residual and stop test (Fig. 1: force residual, iteration count, until
-// converged), plus the optional stall guard.  Returns true when the solve is
-// finished.
-__device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P, double gf2,
-                                          double gb2, double ke2, int64_t n, double &rho,
-                                          double &ke, int &status, Progress &pg)
+// converged), plus the optional stall guard.  rho = |g_free| / max(|g_B|,
+// s_floor) <= tol is tested in squared form, gf2 <= tol^2 max(gb2, s_floor^2),
+// which needs no square root or division in the loop.  Returns true when the
+// solve is finished.
+__device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P, double tol2,
+                                          double gf2, double gb2, double ke2, int64_t n,
+                                          int &status, Progress &pg)
 {
-    double den = sqrt(gb2);
-    if (den < P.s_floor) den = P.s_floor;
-    rho = sqrt(gf2) / den;
-    ke = 0.5 * ke2;
-    if (!isfinite(rho) || !isfinite(ke)) { status = kNonFinite; return true; }
-    if (rho <= A.tol) { status = kConverged; return true; }
+    const double fl2 = P.s_floor * P.s_floor;
+    const double den2 = gb2 > fl2 ? gb2 : fl2;
+    if (!isfinite(gf2) || !isfinite(gb2) || !isfinite(ke2)) { status = kNonFinite; return true; }
+    if (gf2 <= tol2 * den2) { status = kConverged; return true; }
     if (n >= A.max_iter) { status = kMaxIter; return true; }
-    if (rho < pg.best * (1.0 - 1e-3)) {
-        pg.best = rho;
+    // progress: rho^2 below (1 - 1e-3)^2 of the best so far
+    if (gf2 < pg.best * den2 * 0.998001) {
+        pg.best = gf2 / den2;
         pg.nbest = n;
     } else if (A.stall_window > 0 && n - pg.nbest >= A.stall_window) {
         status = kStatusStalled;
         return true;
     }
     return false;
+}
+
+// Reported residual ratio and kinetic energy of the last pass.
+__device__ __forceinline__ void final_scalars(const ProbDesc &P, double gf2, double gb2,
+                                              double ke2, double &rho, double &ke)
+{
+    double den = sqrt(gb2);
+    if (den < P.s_floor) den = P.s_floor;
+    rho = sqrt(gf2) / den;
+    ke = 0.5 * ke2;
 }
 
 // Scalars of the problem after a launch (thread 0 writes).
@@ -482,6 +611,20 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     constexpr int QS = kQStride<T>;
     T *qsave = reinterpret_cast<T *>(A.qbuf) + QS * nb;
     T *wsave = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
+
+    // headers of this wave's NPT slices, read each pass from LDS
+    static_assert(4 + 2 * NPT <= kRedStride, "row headers fit the wave's LDS record");
+    RowHdr *hdr = reinterpret_cast<RowHdr *>(red + wave * kRedStride + 4);
+    if (lane < NPT) {
+        RowHdr h{0, 0, 0};
+        const int r0 = lane * BLOCK + wave * kWave;
+        if (r0 < N) {
+            const int q = r0 >> 6;
+            h.w = A.slice_w[P.slice_base + q];
+            h.e0 = P.inc_base + A.slice_off[P.slice_base + q];
+        }
+        hdr[lane] = h;
+    }
 
     T w[NPT][3];
     T cmp[NPT][3]; // compensation of the FP32 state updates (unused in FP64)
@@ -543,7 +686,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     __syncthreads();
 
     const int64_t n0 = n;
-    double rho = 0.0, ke = 0.0;
+    const double tol2 = A.tol * A.tol;
+    double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
     Progress pg{__builtin_huge_val(), n};
     if (S.start == kResume) {
@@ -570,21 +714,44 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             }
         }
         __syncthreads();
-        double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
+        gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
+        Pref<Prec, CH> pf;
+        {
+            const RowHdr h0 = hdr[0];
+            if (h0.w > 0) pref_load<Prec, CH>(A, h0.e0, h0.w, 0, lane, pf);
+        }
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
             const int r = s * BLOCK + tp;
-            if (s * BLOCK + wave * kWave < N) {
-                const Row row = node_row(A, P, r);
+            const RowHdr h = hdr[s];
+            RowHdr hn{0, 0, 0};
+            if (s + 1 < NPT) hn = hdr[s + 1];
+            if (h.w > 0) {
+                // node state and mass first, so their loads overlap the gather
+                T qi[3] = {0, 0, 0};
+                if (r < N) pos.load(r, qi[0], qi[1], qi[2]);
+                T im = 0;
+                double m = 0.0;
+                if (r < Nf) {
+                    im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+                    m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
+                }
+                T g[3] = {0, 0, 0};
+                for (int k0 = 0; k0 < h.w; k0 += CH) {
+                    const Pref<Prec, CH> cur = pf;
+                    // next chunk: the rest of this row, else the next row, else
+                    // (end of the stream) this row's first chunk again
+                    int64_t ne0 = h.e0;
+                    int nw = h.w, nk = 0;
+                    if (k0 + CH < h.w) nk = k0 + CH;
+                    else if (hn.w > 0) { ne0 = hn.e0; nw = hn.w; }
+                    pref_load<Prec, CH>(A, ne0, nw, nk, lane, pf);
+                    force_chunk<Prec, CH>(cur, af, pos, k0, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
+                }
                 if (r < N) {
-                    T qi[3], g[3];
-                    pos.load(r, qi[0], qi[1], qi[2]);
-                    gather<Prec, CH>(A, af, row, pos, lane, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
                     const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
                                       (double)g[2] * (double)g[2];
                     if (r < Nf) {
-                        const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
-                        const double m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
                         double vv = 0.0;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -600,13 +767,17 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                         gb2 += gg;
                     }
                 }
+            } else if (hn.w > 0) {
+                // an empty row (prescribed nodes without fibers): prime the next
+                pref_load<Prec, CH>(A, hn.e0, hn.w, 0, lane, pf);
             }
         }
         block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
         ++n;
-        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status, pg)) break;
+        if (stop_test(A, P, tol2, gf2, gb2, ke2, n, status, pg)) break;
         if (n - n0 >= A.budget) break;
     }
+    final_scalars(P, gf2, gb2, ke2, rho, ke);
 
     if (status != kStatusRunning) {
 #pragma unroll
@@ -641,8 +812,28 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 // ---------------------------------------------------------------------------
 // Global-placement variant: state and half-step velocities in device memory
 // (L2-resident for one problem), any problem size.
+//
+// The gather of a pass walks each wave's rows (slices i*NW + wave) as one
+// stream of chunks of C incidences in a two-stage software pipeline: while
+// chunk c is formed, the neighbour states of chunk c+1 and the topology of
+// chunk c+2 are in flight, and a row's own node data (state, degree, mass,
+// velocity) is loaded when its first chunk enters the pipeline.  The slice
+// headers sit in LDS when the problem has at most kGlbHdrMax slices.
 // ---------------------------------------------------------------------------
-template <class Prec, int BLOCK>
+template <class Prec> struct KLof;
+template <> struct KLof<P64> { using type = KL; };
+template <> struct KLof<P32> { using type = KL32; };
+
+// A node's data for the force phase.
+template <class T> struct NodeData {
+    T q[3];
+    T w[3];
+    T im;
+    double m;
+    int d;
+};
+
+template <class Prec, int BLOCK, int C>
 __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
 {
     using T = typename Prec::T;
@@ -662,6 +853,52 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     T *Cq = reinterpret_cast<T *>(A.qbuf) + QS * nb + 4; // FP32 compensation terms
     T *W = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
+    using KLT = typename KLof<Prec>::type;
+
+    // slice headers in LDS (the host admits at most kGlbHdrMax slices per
+    // problem and sizes the launch's LDS for the class's largest problem)
+    RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride);
+    for (int q = tid; q < P.n_slices; q += BLOCK)
+        hdr_lds[q] = RowHdr{P.inc_base + A.slice_off[P.slice_base + q], A.slice_w[P.slice_base + q], 0};
+    // rows of this wave: i = 0 .. nrow-1 (node i*BLOCK + tid, slice i*NW + wave)
+    const int nrow = (N - wave * kWave + BLOCK - 1) / BLOCK;
+    auto hdr_of = [&](int i) -> RowHdr { return hdr_lds[i * NW + wave]; };
+    // stream cursor: row i, first incidence k0 of the chunk; i >= nrow = end
+    struct Cur {
+        int i, k0;
+    };
+    auto first_from = [&](int i) -> Cur {
+        while (i < nrow && hdr_of(i).w == 0) ++i;
+        return Cur{i, 0};
+    };
+    auto next = [&](Cur c) -> Cur {
+        if (c.i >= nrow) return c;
+        if (c.k0 + C < hdr_of(c.i).w) return Cur{c.i, c.k0 + C};
+        return first_from(c.i + 1);
+    };
+    auto topo = [&](Cur c, Cur dummy, Pref<Prec, C> &pf) {
+        const Cur x = c.i < nrow ? c : dummy;
+        const RowHdr h = hdr_of(x.i);
+        pref_load<Prec, C>(A, h.e0, h.w, x.k0, lane, pf);
+    };
+    auto node_data = [&](int i, NodeData<T> &nd) {
+        const int r = i * BLOCK + tid;
+        nd.q[0] = nd.q[1] = nd.q[2] = 0;
+        nd.w[0] = nd.w[1] = nd.w[2] = 0;
+        nd.im = 0;
+        nd.m = 0.0;
+        nd.d = 0;
+        if (r < N) {
+            pos.load(r, nd.q[0], nd.q[1], nd.q[2]);
+            nd.d = A.deg[nb + r];
+            if (r < Nf) {
+                nd.im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+                nd.m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nd.w[a] = W[4 * r + a];
+            }
+        }
+    };
 
     int64_t n = 0;
     if (S.start != kResume) {
@@ -689,7 +926,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     __syncthreads();
 
     const int64_t n0 = n;
-    double rho = 0.0, ke = 0.0;
+    const double tol2 = A.tol * A.tol;
+    double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
     Progress pg{__builtin_huge_val(), n};
     if (S.start == kResume) {
@@ -709,37 +947,85 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 for (int a = 0; a < 3; ++a) Cq[QS * r + a] = c[a];
         }
         __syncthreads();
-        double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
-        for (int r = tid; r < N; r += BLOCK) {
-            T qi[3], g[3];
-            pos.load(r, qi[0], qi[1], qi[2]);
-            gather<Prec, 4>(A, af, node_row(A, P, r), pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
-                         g[1], g[2]);
-            const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
-                              (double)g[2] * (double)g[2];
-            if (r < Nf) {
-                const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
-                const double m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
-                double vv = 0.0;
+        gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
+        const Cur cfirst = first_from(0);
+        if (cfirst.i < nrow) {
+            // prologue: topology and neighbour states of chunk c0, topology of c1
+            Cur c0 = cfirst;
+            Pref<Prec, C> t0, t1;
+            topo(c0, cfirst, t0);
+            Cur c1 = next(c0);
+            topo(c1, cfirst, t1);
+            NodeData<T> n0, n1;
+            node_data(c0.i, n0);
+            KLT k0c[C];
+            T px0[C], py0[C], pz0[C];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T wa = W[4 * r + a];
-                    const T acc = g[a] * im - cdamp * wa;
-                    const T v = wa + hdt * acc;
-                    vv += (double)v * (double)v;
-                    W[4 * r + a] = v + hdt * acc;
+            for (int t = 0; t < C; ++t) {
+                pos.load(t0.j[t], px0[t], py0[t], pz0[t]);
+                k0c[t] = t0.c[t];
+            }
+            T g[3] = {0, 0, 0};
+            for (;;) {
+                // stage 1: neighbour states (and new row's node data) of c1
+                KLT k1c[C];
+                T px1[C], py1[C], pz1[C];
+#pragma unroll
+                for (int t = 0; t < C; ++t) {
+                    pos.load(t1.j[t], px1[t], py1[t], pz1[t]);
+                    k1c[t] = t1.c[t];
                 }
-                gf2 += gg;
-                ke2 += m * vv;
-            } else {
-                gb2 += gg;
+                const bool c1_valid = c1.i < nrow;
+                const bool c1_new_row = c1_valid && c1.i != c0.i;
+                if (c1_new_row) node_data(c1.i, n1);
+                // stage 2: topology of c2
+                const Cur c2 = next(c1);
+                topo(c2, cfirst, t1);
+                // stage 3: forces of c0
+                force_pre<C>(k0c, px0, py0, pz0, af, c0.k0, n0.d, n0.q[0], n0.q[1], n0.q[2], g[0],
+                             g[1], g[2]);
+                if (!c1_valid || c1_new_row) {
+                    // c0 was the last chunk of its row: the node's damped
+                    // acceleration, velocity updates and norm shares
+                    const int r = c0.i * BLOCK + tid;
+                    if (r < N) {
+                        const double gg = (double)g[0] * (double)g[0] +
+                                          (double)g[1] * (double)g[1] +
+                                          (double)g[2] * (double)g[2];
+                        if (r < Nf) {
+                            double vv = 0.0;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const T acc = g[a] * n0.im - cdamp * n0.w[a];
+                                const T v = n0.w[a] + hdt * acc;
+                                vv += (double)v * (double)v;
+                                W[4 * r + a] = v + hdt * acc;
+                            }
+                            gf2 += gg;
+                            ke2 += n0.m * vv;
+                        } else {
+                            gb2 += gg;
+                        }
+                    }
+                    g[0] = g[1] = g[2] = 0;
+                    if (!c1_valid) break;
+                    n0 = n1;
+                }
+                c0 = c1;
+                c1 = c2;
+#pragma unroll
+                for (int t = 0; t < C; ++t) {
+                    k0c[t] = k1c[t];
+                    px0[t] = px1[t]; py0[t] = py1[t]; pz0[t] = pz1[t];
+                }
             }
         }
         block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
         ++n;
-        if (stop_test(A, P, gf2, gb2, ke2, n, rho, ke, status, pg)) break;
+        if (stop_test(A, P, tol2, gf2, gb2, ke2, n, status, pg)) break;
         if (n - n0 >= A.budget) break;
     }
+    final_scalars(P, gf2, gb2, ke2, rho, ke);
 
     if (status != kStatusRunning) {
         for (int r = tid; r < N; r += BLOCK) {
@@ -944,7 +1230,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_finish(SolveArgs A, int slo
         pos.load(r, q[0], q[1], q[2]);
         write_u<P64>(A, S, r, q);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) record(A, S, n, rho, ke, status, Progress{rho, n});
+    if (blockIdx.x == 0 && threadIdx.x == 0) record(A, S, n, rho, ke, status, Progress{rho * rho, n});
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
@@ -972,7 +1258,24 @@ template <class P, int B, int NP>
 static int launch_reg_np(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
 {
     if (pl.chunk == 4) return launch(k_dr_reg<P, B, NP, 4>, a.n_solve, B, pl.lds_bytes, st, a);
+    if (pl.chunk == 1) return launch(k_dr_reg<P, B, NP, 1>, a.n_solve, B, pl.lds_bytes, st, a);
     return launch(k_dr_reg<P, B, NP, 2>, a.n_solve, B, pl.lds_bytes, st, a);
+}
+
+// The 256-thread global variant is built with chunks of 1 only: its chunk-2
+// and chunk-4 builds gave wrong states on multi-row problems while every
+// other shape matched bit for bit (the host plans chunk 1 for it).
+template <class P, int B>
+static int launch_glb(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
+{
+    if constexpr (B == 256) {
+        if (pl.chunk != 1) return -1002;
+        return launch(k_dr_glb<P, B, 1>, a.n_solve, B, pl.lds_bytes, st, a);
+    } else {
+        if (pl.chunk == 4) return launch(k_dr_glb<P, B, 4>, a.n_solve, B, pl.lds_bytes, st, a);
+        if (pl.chunk == 1) return launch(k_dr_glb<P, B, 1>, a.n_solve, B, pl.lds_bytes, st, a);
+        return launch(k_dr_glb<P, B, 2>, a.n_solve, B, pl.lds_bytes, st, a);
+    }
 }
 
 template <class P, int B>
@@ -1003,9 +1306,9 @@ static int launch_dr(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
         }
     }
     switch (pl.block) {
-    case 256: return launch(k_dr_glb<P, 256>, a.n_solve, 256, pl.lds_bytes, st, a);
-    case 512: return launch(k_dr_glb<P, 512>, a.n_solve, 512, pl.lds_bytes, st, a);
-    case 1024: return launch(k_dr_glb<P, 1024>, a.n_solve, 1024, pl.lds_bytes, st, a);
+    case 256: return launch_glb<P, 256>(a, pl, st);
+    case 512: return launch_glb<P, 512>(a, pl, st);
+    case 1024: return launch_glb<P, 1024>(a, pl, st);
     default: return -1001;
     }
 }
@@ -1060,6 +1363,7 @@ const char *kernel_error_string(int code)
 {
     if (code == -1000) return "no kernel instantiated for this nodes-per-thread count";
     if (code == -1001) return "unsupported workgroup size";
+    if (code == -1002) return "no global-placement kernel for this chunk at 256 threads";
     return hipGetErrorString((hipError_t)code);
 }
 

@@ -22,6 +22,10 @@
 namespace drk {
 
 constexpr int kWave = 64;
+// Largest slice count of one problem: the global-placement kernel keeps the
+// problem's slice headers (16 B each) in LDS, so a problem has at most
+// 64 * kGlbHdrMax = 524288 nodes.
+constexpr int kGlbHdrMax = 8192;
 
 // Per-problem status values beyond dr_result: a solve that has been started
 // and stopped at a pass budget, and a problem with no solve yet.
@@ -107,7 +111,7 @@ struct LaunchPlan {
     int block;     // threads per workgroup
     int npt;       // nodes per thread (register-resident variant), 0 = global
     int lds_bytes; // dynamic LDS per workgroup
-    int chunk;     // incidences gathered per unconditional chunk (2 or 4)
+    int chunk;     // incidences per pipelined gather step (1, 2 or 4)
     int fp32;      // 1: FP32 nodal state and force gather
 };
 

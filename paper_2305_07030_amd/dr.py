@@ -73,6 +73,12 @@ def load():
     path = _build.LIB
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2305_07030_amd.build.build()")
+    # PyTorch's HIP runtime (same soname as the one libdr links) is loaded
+    # first, so the library and torch's streams and memory share one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.dr_options_default.argtypes = [C.POINTER(dr_options)]

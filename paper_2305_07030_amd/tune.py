@@ -33,7 +33,7 @@ from . import dr
 # separates the LDS-resident and global placements.
 DEFAULT_EDGES = (256, 512, 1024, 2048, 4096, 6720, 8192, 16384, 32768)
 BLOCKS = (256, 512, 1024)
-CHUNKS = (2, 4)
+CHUNKS = (1, 2, 4)
 
 
 @dataclass(frozen=True)
@@ -92,7 +92,8 @@ def device_key(precision: int) -> str:
 def time_plan(sub, plan: Plan, *, passes: int, precision: int, reps: int,
               clock: Callable[[], float] = time.perf_counter) -> Optional[float]:
     """Median wall time of one fixed-pass launch over the sub-batch with this
-    plan, or None when the library rejects the plan for it."""
+    plan, or None when the library rejects the plan for it or a problem of the
+    sample does not complete the passes."""
     n_hi = max(n.n_nodes for n in sub.nets)
     b = dr.DRBatch(sub, tol=1e-300, max_iter=passes, precision=precision)
     try:
@@ -104,6 +105,9 @@ def time_plan(sub, plan: Plan, *, passes: int, precision: int, reps: int,
             raise
         b.solve()
         b.sync()  # warm-up
+        # a plan must run the sample's passes to the end (no early stop)
+        if not (b.results()["result"] == dr.DR_MAX_ITER).all():
+            return None
         ts = []
         for _ in range(reps):
             t0 = clock()

@@ -80,6 +80,10 @@ def test_rejects_bad_networks(lib):
     _expect_invalid(I.Batch([net], np.eye(3)[None]).packed(), match="node 3 is free but has no fiber")
     bad = dict(pk); bad["node_offsets"] = pk["node_offsets"].copy(); bad["node_offsets"][2] = bad["node_offsets"][1]
     _expect_invalid(bad, match="has no nodes")
+    # more nodes than one problem may have (the offsets alone are checked first)
+    bad = dict(pk); bad["node_offsets"] = pk["node_offsets"].copy(); bad["node_offsets"][1] = 524289
+    bad["node_offsets"][2:] = np.maximum(bad["node_offsets"][2:], 524289)
+    _expect_invalid(bad, match="at most 524288 per problem")
 
 
 def test_rejects_bad_options(lib):

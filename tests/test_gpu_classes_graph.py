@@ -144,3 +144,35 @@ def test_tuned_plans_apply_and_match_oracle(tmp_path):
         assert g["result"][i] == dr.DR_CONVERGED and o.status == O.CONVERGED
         assert abs(int(g["iters"][i]) - o.iters) <= 1 + 2e-3 * o.iters
         assert rel(g["sigma"][i], o.sigma) < 1e-8
+
+
+def test_all_launch_shapes_same_bits():
+    """Every launch shape computes the same per-node arithmetic in the same
+    order, so after a fixed pass count the states agree bit for bit across
+    blocks, gather chunks and placements (sizes span one to several rows of
+    slices per wave)."""
+    rng = np.random.default_rng(64)
+    nets = [I.draw_network(rng, n) for n in (120, 300, 900, 2600)]
+    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
+    K = 300
+    ref = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=1e-3, block=1024, chunk=1,
+                     placement=dr.DR_PLACE_LDS)
+    ref.solve()
+    R = ref.results(want_u=True)
+    assert (R["result"] == dr.DR_MAX_ITER).all()
+    for place in (dr.DR_PLACE_LDS, dr.DR_PLACE_GLOBAL):
+        for blk in (256, 512, 1024):
+            for ch in (1, 2, 4):
+                try:
+                    b = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=1e-3, block=blk, chunk=ch,
+                                   placement=place)
+                except dr.DrError as e:
+                    assert place == dr.DR_PLACE_LDS and e.status == dr.DR_E_INVALID
+                    continue
+                b.solve()
+                g = b.results(want_u=True)
+                say(f"placement {place} block {blk} chunk {ch}: status {g['result'].tolist()}")
+                assert (g["result"] == dr.DR_MAX_ITER).all()
+                assert np.array_equal(g["u"], R["u"]), (place, blk, ch)
+                assert np.array_equal(g["sigma"], R["sigma"]), (place, blk, ch)
+                b.close()
