@@ -246,7 +246,10 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
         const double *EA = nets->EA + fo[p];
         const uint8_t *fixed = nets->fixed + no[p];
 
-        std::vector<double> L(M), L2(M);
+        // L2g: L^2 rounded as the kernels form squared lengths,
+        // fma(dz, dz, fma(dy, dy, dx * dx)), so that l^2 - L^2 is exactly 0
+        // for a fiber at its reference length
+        std::vector<double> L(M), L2(M), L2g(M);
         std::vector<int32_t> degree(N, 0);
         for (int32_t f = 0; f < M; ++f) {
             const int32_t a = fib[2 * f], b = fib[2 * f + 1];
@@ -260,6 +263,7 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
             const double dx = X[3 * b] - X[3 * a], dy = X[3 * b + 1] - X[3 * a + 1],
                          dz = X[3 * b + 2] - X[3 * a + 2];
             L2[f] = dx * dx + dy * dy + dz * dz;
+            L2g[f] = std::fma(dz, dz, std::fma(dy, dy, dx * dx));
             L[f] = std::sqrt(L2[f]);
             if (!(L[f] > 0.0))
                 return fail(DR_E_INVALID, "problem %d fiber %d has zero reference length", p, f);
@@ -372,11 +376,38 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
                     const size_t e = base + (size_t)k * drk::kWave + lane;
                     pk.nbr[e] = h.new_of_old[other];
                     const double kf = EA[f] / (2.0 * L2[f]);
-                    pk.kl[e] = KL{kf, L2[f]};
+                    pk.kl[e] = KL{kf, L2g[f]};
                     if (fp32)
                         pk.kl32[e] = KL32{(float)(X[3 * other] - X[3 * i]),
                                           (float)(X[3 * other + 1] - X[3 * i + 1]),
                                           (float)(X[3 * other + 2] - X[3 * i + 2]), (float)kf};
+                }
+                // Padding up to the slice width: zero constants and a
+                // neighbour at a positive distance (the first real neighbour,
+                // or for a node without fibers another node at a different
+                // reference point), so the entry adds exactly zero force.
+                if (degree[i] < width) {
+                    int32_t pad = -1;
+                    if (degree[i] > 0) {
+                        const int32_t f = ent[rp[i]];
+                        pad = fib[2 * f] == i ? fib[2 * f + 1] : fib[2 * f];
+                    } else {
+                        for (int32_t j = 0; j < N && pad < 0; ++j)
+                            if (X[3 * j] != X[3 * i] || X[3 * j + 1] != X[3 * i + 1] ||
+                                X[3 * j + 2] != X[3 * i + 2])
+                                pad = j;
+                        if (pad < 0)
+                            return fail(DR_E_INVALID,
+                                        "problem %d: every node sits at the same reference point", p);
+                    }
+                    for (int32_t k = degree[i]; k < width; ++k) {
+                        const size_t e = base + (size_t)k * drk::kWave + lane;
+                        pk.nbr[e] = h.new_of_old[pad];
+                        if (fp32)
+                            pk.kl32[e] = KL32{(float)(X[3 * pad] - X[3 * i]),
+                                              (float)(X[3 * pad + 1] - X[3 * i + 1]),
+                                              (float)(X[3 * pad + 2] - X[3 * i + 2]), 0.f};
+                    }
                 }
             }
             off += (int64_t)width * drk::kWave;

@@ -19,7 +19,7 @@
 // separate launch (k_stress) forms the reactions and both stress forms.
 //
 // Placements:
-//   k_dr_reg<P, BLOCK, NPT, CH>: state q in LDS (SoA), the half-step velocity
+//   k_dr_reg<P, BLOCK, NPT, CH>: state q in LDS (24 B per node), the half-step velocity
 //     and degree of each owned node in registers, NPT nodes per thread;
 //   k_dr_glb<P, BLOCK>: state and velocities in device memory, any size.
 // Precision policies:
@@ -71,12 +71,24 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Squared length, rounded as the host rounds L^2 (no fused multiply-add), so
-// a fiber at its reference length carries exactly zero force.
+// Squared length fma(dz, dz, fma(dy, dy, dx * dx)).  The host forms the L^2
+// of every incidence with the same operations in the same order, so a fiber
+// at its reference length carries exactly zero force.
 __device__ __forceinline__ double len2(double dx, double dy, double dz)
 {
 #pragma clang fp contract(off)
-    return dx * dx + dy * dy + dz * dz;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by one
+// second-order Householder step, e = 1 - x y^2, y <- y + y e (1/2 + 3/8 e)
+// (no special-case handling: every l^2 reaching it is positive).
+__device__ __forceinline__ double rsq64(double x)
+{
+#pragma clang fp contract(off)
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 struct P64 {
@@ -88,17 +100,20 @@ struct P32 {
     static constexpr bool kDisp = true;
 };
 
-// Running state of one problem in LDS, SoA.
+// Running state of one problem in LDS: 3 values per node, node after node
+// (one address per node, the components at immediate offsets).
 template <class T> struct LdsQ {
     T *a;
     int n;
     __device__ __forceinline__ void load(int j, T &x, T &y, T &z) const
     {
-        x = a[j]; y = a[n + j]; z = a[2 * n + j];
+        const T *q = a + 3 * j;
+        x = q[0]; y = q[1]; z = q[2];
     }
     __device__ __forceinline__ void store(int j, T x, T y, T z) const
     {
-        a[j] = x; a[n + j] = y; a[2 * n + j] = z;
+        T *q = a + 3 * j;
+        q[0] = x; q[1] = y; q[2] = z;
     }
 };
 
@@ -185,7 +200,7 @@ __device__ __forceinline__ void chunk64(const SolveArgs &A, int64_t e, const Pos
 #pragma unroll
     for (int t = 0; t < C; ++t) {
         const double l2 = len2(dx[t], dy[t], dz[t]);
-        double s = c[t].k * (l2 - c[t].L2) * rsqrt(l2);
+        double s = c[t].k * (l2 - c[t].L2) * rsq64(l2);
         s = (k0 + t < d) ? s : 0.0;
         gx += s * dx[t]; gy += s * dy[t]; gz += s * dz[t];
         if (STRESS) {
@@ -308,92 +323,110 @@ __device__ __forceinline__ void gather_stress(const SolveArgs &A, const Row &row
 }
 
 // ---------------------------------------------------------------------------
-// Software-pipelined gather of the register-resident kernel.  The rows of a
-// thread's NPT nodes are walked as one stream of chunks of C incidences; the
-// neighbour ids and constants of the next chunk are loaded before the current
-// chunk's positions are read and its forces formed, so the L2 latency of the
-// topology overlaps the work instead of preceding it.  Entries past a row's
-// width are clamped to its last entry (always a valid address) and masked by
-// the node's degree like the padding.
+// Software-pipelined gather of the pass loops.  A wave's rows are walked as
+// one stream of chunks of C incidences; the neighbour ids and constants of
+// the next chunk are loaded before the current chunk's neighbour states are
+// read and its forces formed.  Every entry of a row up to the slice width is
+// summed: padding entries carry zero constants and point at a real
+// neighbour of the node (a positive length), so they add exactly zero and
+// need no per-lane mask; entries past the width (the last chunk of a row) are
+// skipped by a wave-uniform test.  Loads use the problem's base pointers
+// (uniform) and 32-bit per-lane offsets.
 // ---------------------------------------------------------------------------
-template <class Prec, int C> struct Pref;
-template <int C> struct Pref<P64, C> {
+template <class Prec> struct KLof;
+template <> struct KLof<P64> { using type = KL; };
+template <> struct KLof<P32> { using type = KL32; };
+
+template <class Prec, int C> struct Pref {
     int j[C];
-    KL c[C];
-};
-template <int C> struct Pref<P32, C> {
-    int j[C];
-    KL32 c[C];
+    typename KLof<Prec>::type c[C];
 };
 
-// Header of one slice (wave-uniform), kept in LDS for the whole solve.
+// Header of one slice (wave-uniform): first entry relative to the problem's
+// incidence base, and width (0: no such slice for this wave).
 struct RowHdr {
-    int64_t e0; // first entry of the slice
-    int32_t w;  // width (0: no such slice for this wave)
-    int32_t pad;
+    uint32_t off;
+    int32_t w;
 };
 
+// A header read from LDS, made wave-uniform (scalar registers).
+__device__ __forceinline__ RowHdr uniform_hdr(const RowHdr *p)
+{
+    const RowHdr h = *p;
+    return RowHdr{(uint32_t)__builtin_amdgcn_readfirstlane((int)h.off),
+                  __builtin_amdgcn_readfirstlane(h.w)};
+}
+
+// Base pointers of one problem's incidence arrays.
+template <class Prec> struct Topo {
+    const int32_t *nbr;
+    const typename KLof<Prec>::type *kl;
+};
+
+template <class Prec>
+__device__ __forceinline__ Topo<Prec> topo_of(const SolveArgs &A, const ProbDesc &P)
+{
+    Topo<Prec> t;
+    t.nbr = A.nbr + P.inc_base;
+    if constexpr (Prec::kDisp) t.kl = A.kl32 + P.inc_base;
+    else t.kl = A.kl + P.inc_base;
+    return t;
+}
+
+// Loads entries k0 .. k0+C-1 of a row (clamped to its last entry): the
+// row's entry k starts at a uniform address, the lane indexes into it.
 template <class Prec, int C>
-__device__ __forceinline__ void pref_load(const SolveArgs &A, int64_t e0, int w, int k0, int lane,
+__device__ __forceinline__ void pref_load(const Topo<Prec> &tp, RowHdr h, int k0, int lane,
                                           Pref<Prec, C> &pf)
 {
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-        const int k = k0 + t < w ? k0 + t : w - 1;
-        const int64_t e = e0 + (int64_t)k * kWave + lane;
-        pf.j[t] = A.nbr[e];
-        if constexpr (Prec::kDisp) pf.c[t] = A.kl32[e];
-        else pf.c[t] = A.kl[e];
+        const int k = k0 + t < h.w ? k0 + t : h.w - 1;
+        const uint32_t e = h.off + (uint32_t)(k * kWave); // uniform
+        pf.j[t] = (tp.nbr + e)[lane];
+        pf.c[t] = (tp.kl + e)[lane];
     }
 }
 
-// Forces of one chunk whose neighbour states px, py, pz are loaded (same
-// arithmetic and order as chunk64 / chunk32).
+// Forces of the first nv (>= 1) entries of one chunk whose neighbour states
+// px, py, pz are loaded, added in entry order.
 template <int C>
 __device__ __forceinline__ void force_pre(const KL (&c)[C], const double (&px)[C],
                                           const double (&py)[C], const double (&pz)[C],
-                                          const Aff32 &, int k0, int d, double xi, double yi,
-                                          double zi, double &gx, double &gy, double &gz)
+                                          const Aff32 &, int nv, double xi, double yi, double zi,
+                                          double &gx, double &gy, double &gz)
 {
-    double dx[C], dy[C], dz[C];
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-        dx[t] = px[t] - xi; dy[t] = py[t] - yi; dz[t] = pz[t] - zi;
-    }
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
-        const double l2 = len2(dx[t], dy[t], dz[t]);
-        double s = c[t].k * (l2 - c[t].L2) * rsqrt(l2);
-        s = (k0 + t < d) ? s : 0.0;
-        gx += s * dx[t]; gy += s * dy[t]; gz += s * dz[t];
+        if (t > 0 && t >= nv) break;
+        const double dx = px[t] - xi, dy = py[t] - yi, dz = pz[t] - zi;
+        const double l2 = len2(dx, dy, dz);
+        const double s = c[t].k * (l2 - c[t].L2) * rsq64(l2);
+        gx += s * dx; gy += s * dy; gz += s * dz;
     }
 }
 
 template <int C>
 __device__ __forceinline__ void force_pre(const KL32 (&c)[C], const float (&px)[C],
                                           const float (&py)[C], const float (&pz)[C],
-                                          const Aff32 &af, int k0, int d, float qi0, float qi1,
-                                          float qi2, float &gx, float &gy, float &gz)
+                                          const Aff32 &af, int nv, float qi0, float qi1, float qi2,
+                                          float &gx, float &gy, float &gz)
 {
-    float dq0[C], dq1[C], dq2[C];
 #pragma unroll
     for (int t = 0; t < C; ++t) {
-        dq0[t] = px[t] - qi0; dq1[t] = py[t] - qi1; dq2[t] = pz[t] - qi2;
-    }
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
+        if (t > 0 && t >= nv) break;
+        const float dq0 = px[t] - qi0, dq1 = py[t] - qi1, dq2 = pz[t] - qi2;
         const float X0 = c[t].dx, X1 = c[t].dy, X2 = c[t].dz;
         const float f0 = af.F[0] * X0 + af.F[1] * X1 + af.F[2] * X2;
         const float f1 = af.F[3] * X0 + af.F[4] * X1 + af.F[5] * X2;
         const float f2 = af.F[6] * X0 + af.F[7] * X1 + af.F[8] * X2;
         const float eaff = af.C[0] * X0 * X0 + af.C[1] * X1 * X1 + af.C[2] * X2 * X2 +
                            af.C[3] * X0 * X1 + af.C[4] * X0 * X2 + af.C[5] * X1 * X2;
-        const float ex = eaff + 2.0f * (f0 * dq0[t] + f1 * dq1[t] + f2 * dq2[t]) +
-                         (dq0[t] * dq0[t] + dq1[t] * dq1[t] + dq2[t] * dq2[t]);
-        const float dx = f0 + dq0[t], dy = f1 + dq1[t], dz = f2 + dq2[t];
+        const float ex = eaff + 2.0f * (f0 * dq0 + f1 * dq1 + f2 * dq2) +
+                         (dq0 * dq0 + dq1 * dq1 + dq2 * dq2);
+        const float dx = f0 + dq0, dy = f1 + dq1, dz = f2 + dq2;
         const float l2 = dx * dx + dy * dy + dz * dz;
-        float s = c[t].k * ex * rsqrtf(l2);
-        s = (k0 + t < d) ? s : 0.0f;
+        const float s = c[t].k * ex * rsqrtf(l2);
         gx += s * dx; gy += s * dy; gz += s * dz;
     }
 }
@@ -402,13 +435,13 @@ __device__ __forceinline__ void force_pre(const KL32 (&c)[C], const float (&px)[
 // force_pre.
 template <class Prec, int C, class Pos, class T = typename Prec::T>
 __device__ __forceinline__ void force_chunk(const Pref<Prec, C> &pf, const Aff32 &af,
-                                            const Pos &pos, int k0, int d, T qi0, T qi1, T qi2,
-                                            T &gx, T &gy, T &gz)
+                                            const Pos &pos, int nv, T qi0, T qi1, T qi2, T &gx,
+                                            T &gy, T &gz)
 {
     T px[C], py[C], pz[C];
 #pragma unroll
     for (int t = 0; t < C; ++t) pos.load(pf.j[t], px[t], py[t], pz[t]);
-    force_pre<C>(pf.c, px, py, pz, af, k0, d, qi0, qi1, qi2, gx, gy, gz);
+    force_pre<C>(pf.c, px, py, pz, af, nv, qi0, qi1, qi2, gx, gy, gz);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,31 +536,40 @@ __device__ __forceinline__ double lane0(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Block-wide sums of three values; every thread returns the same totals.
-// Each wave reduces its lanes, lane 0 posts the partials; after the barrier
-// every wave reduces the NW partials over its lanes 0..NW-1 (the same inputs
-// in the same lanes, so the same rounding in every wave) and takes lane 0's
-// result, so all threads agree bit for bit.
+// Block-wide sums; every thread returns the same totals.  Each wave reduces
+// its lanes and lane 0 posts the partials; after the barrier every wave
+// reduces the NW partials over its lanes 0..NW-1 (the same inputs in the
+// same lanes, so the same rounding in every wave) and takes lane 0's
+// result, so all threads agree bit for bit.  The caller guarantees that no
+// thread still reads the previous sums (a barrier since their last use).
 template <int NW>
-__device__ __forceinline__ void block_sum3(double *red, int lane, int wave, double &a, double &b,
-                                           double &c)
+__device__ __forceinline__ void block_sum2(double *red, int lane, int wave, double &a, double &b)
 {
-    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+    a = wave_sum(a); b = wave_sum(b);
     if (lane == 0) {
         red[wave * kRedStride + 0] = a;
         red[wave * kRedStride + 1] = b;
-        red[wave * kRedStride + 2] = c;
     }
     __syncthreads();
-    double ta = 0.0, tb = 0.0, tc = 0.0;
+    double ta = 0.0, tb = 0.0;
     if (lane < NW) {
         ta = red[lane * kRedStride + 0];
         tb = red[lane * kRedStride + 1];
-        tc = red[lane * kRedStride + 2];
     }
     a = lane0(wave_sum(ta));
     b = lane0(wave_sum(tb));
-    c = lane0(wave_sum(tc));
+}
+
+// One block-wide sum, with a barrier first (callable right after block_sum2).
+template <int NW>
+__device__ __forceinline__ double block_sum1(double *red, int lane, int wave, double a)
+{
+    __syncthreads();
+    a = wave_sum(a);
+    if (lane == 0) red[wave * kRedStride + 2] = a;
+    __syncthreads();
+    const double t = lane < NW ? red[lane * kRedStride + 2] : 0.0;
+    return lane0(wave_sum(t));
 }
 
 // Residual and stop test (Fig. 1: force residual, iteration count, until
@@ -536,12 +578,12 @@ __device__ __forceinline__ void block_sum3(double *red, int lane, int wave, doub
 // which needs no square root or division in the loop.  Returns true when the
 // solve is finished.
 __device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P, double tol2,
-                                          double gf2, double gb2, double ke2, int64_t n,
-                                          int &status, Progress &pg)
+                                          double gf2, double gb2, int64_t n, int &status,
+                                          Progress &pg)
 {
     const double fl2 = P.s_floor * P.s_floor;
     const double den2 = gb2 > fl2 ? gb2 : fl2;
-    if (!isfinite(gf2) || !isfinite(gb2) || !isfinite(ke2)) { status = kNonFinite; return true; }
+    if (!isfinite(gf2) || !isfinite(gb2)) { status = kNonFinite; return true; }
     if (gf2 <= tol2 * den2) { status = kConverged; return true; }
     if (n >= A.max_iter) { status = kMaxIter; return true; }
     // progress: rho^2 below (1 - 1e-3)^2 of the best so far
@@ -613,22 +655,22 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     T *wsave = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
 
     // headers of this wave's NPT slices, read each pass from LDS
-    static_assert(4 + 2 * NPT <= kRedStride, "row headers fit the wave's LDS record");
+    static_assert(4 + NPT <= kRedStride, "row headers fit the wave's LDS record");
     RowHdr *hdr = reinterpret_cast<RowHdr *>(red + wave * kRedStride + 4);
     if (lane < NPT) {
-        RowHdr h{0, 0, 0};
+        RowHdr h{0, 0};
         const int r0 = lane * BLOCK + wave * kWave;
         if (r0 < N) {
             const int q = r0 >> 6;
             h.w = A.slice_w[P.slice_base + q];
-            h.e0 = P.inc_base + A.slice_off[P.slice_base + q];
+            h.off = (uint32_t)A.slice_off[P.slice_base + q];
         }
         hdr[lane] = h;
     }
+    const Topo<Prec> topo = topo_of<Prec>(A, P);
 
     T w[NPT][3];
     T cmp[NPT][3]; // compensation of the FP32 state updates (unused in FP64)
-    int dg[NPT];
     int64_t n = 0;
     if (S.start != kResume) {
 #pragma unroll
@@ -636,12 +678,10 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             const int r = s * BLOCK + tid;
             w[s][0] = w[s][1] = w[s][2] = 0;
             cmp[s][0] = cmp[s][1] = cmp[s][2] = 0;
-            dg[s] = 0;
             if (r < N) {
                 T q[3];
                 start_q<Prec>(A, S, r, q);
                 pos.store(r, q[0], q[1], q[2]);
-                dg[s] = A.deg[nb + r];
             }
         }
         if (tid == 0) begin_solve(A, S);
@@ -657,7 +697,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 if (r < Nf) {
                     T qi[3], g[3];
                     pos.load(r, qi[0], qi[1], qi[2]);
-                    gather<Prec, CH>(A, af, row, pos, lane, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
+                    gather<Prec, CH>(A, af, row, pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
+                                     g[1], g[2]);
                     const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) w[s][a] = hdt * (g[a] * im);
@@ -671,7 +712,6 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             const int r = s * BLOCK + tid;
             w[s][0] = w[s][1] = w[s][2] = 0;
             cmp[s][0] = cmp[s][1] = cmp[s][2] = 0;
-            dg[s] = 0;
             if (r < N) {
                 pos.store(r, qsave[QS * r], qsave[QS * r + 1], qsave[QS * r + 2]);
 #pragma unroll
@@ -679,7 +719,6 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                     w[s][a] = wsave[4 * r + a];
                     if constexpr (Prec::kDisp) cmp[s][a] = qsave[QS * r + 4 + a];
                 }
-                dg[s] = A.deg[nb + r];
             }
         }
     }
@@ -717,15 +756,15 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         Pref<Prec, CH> pf;
         {
-            const RowHdr h0 = hdr[0];
-            if (h0.w > 0) pref_load<Prec, CH>(A, h0.e0, h0.w, 0, lane, pf);
+            const RowHdr h0 = uniform_hdr(hdr);
+            if (h0.w > 0) pref_load<Prec, CH>(topo, h0, 0, lane, pf);
         }
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
             const int r = s * BLOCK + tp;
-            const RowHdr h = hdr[s];
-            RowHdr hn{0, 0, 0};
-            if (s + 1 < NPT) hn = hdr[s + 1];
+            const RowHdr h = uniform_hdr(hdr + s);
+            RowHdr hn{0, 0};
+            if (s + 1 < NPT) hn = uniform_hdr(hdr + s + 1);
             if (h.w > 0) {
                 // node state and mass first, so their loads overlap the gather
                 T qi[3] = {0, 0, 0};
@@ -741,12 +780,12 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                     const Pref<Prec, CH> cur = pf;
                     // next chunk: the rest of this row, else the next row, else
                     // (end of the stream) this row's first chunk again
-                    int64_t ne0 = h.e0;
-                    int nw = h.w, nk = 0;
+                    RowHdr nh = h;
+                    int nk = 0;
                     if (k0 + CH < h.w) nk = k0 + CH;
-                    else if (hn.w > 0) { ne0 = hn.e0; nw = hn.w; }
-                    pref_load<Prec, CH>(A, ne0, nw, nk, lane, pf);
-                    force_chunk<Prec, CH>(cur, af, pos, k0, dg[s], qi[0], qi[1], qi[2], g[0], g[1], g[2]);
+                    else if (hn.w > 0) nh = hn;
+                    pref_load<Prec, CH>(topo, nh, nk, lane, pf);
+                    force_chunk<Prec, CH>(cur, af, pos, h.w - k0, qi[0], qi[1], qi[2], g[0], g[1], g[2]);
                 }
                 if (r < N) {
                     const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
@@ -769,14 +808,16 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 }
             } else if (hn.w > 0) {
                 // an empty row (prescribed nodes without fibers): prime the next
-                pref_load<Prec, CH>(A, hn.e0, hn.w, 0, lane, pf);
+                pref_load<Prec, CH>(topo, hn, 0, lane, pf);
             }
         }
-        block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
+        block_sum2<NW>(red, lane, wave, gf2, gb2);
         ++n;
-        if (stop_test(A, P, tol2, gf2, gb2, ke2, n, status, pg)) break;
+        if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (n - n0 >= A.budget) break;
     }
+    // kinetic energy of the last pass (reported only)
+    ke2 = block_sum1<NW>(red, lane, wave, ke2);
     final_scalars(P, gf2, gb2, ke2, rho, ke);
 
     if (status != kStatusRunning) {
@@ -820,17 +861,12 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 // velocity) is loaded when its first chunk enters the pipeline.  The slice
 // headers sit in LDS when the problem has at most kGlbHdrMax slices.
 // ---------------------------------------------------------------------------
-template <class Prec> struct KLof;
-template <> struct KLof<P64> { using type = KL; };
-template <> struct KLof<P32> { using type = KL32; };
-
 // A node's data for the force phase.
 template <class T> struct NodeData {
     T q[3];
     T w[3];
     T im;
     double m;
-    int d;
 };
 
 template <class Prec, int BLOCK, int C>
@@ -859,27 +895,29 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     // problem and sizes the launch's LDS for the class's largest problem)
     RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride);
     for (int q = tid; q < P.n_slices; q += BLOCK)
-        hdr_lds[q] = RowHdr{P.inc_base + A.slice_off[P.slice_base + q], A.slice_w[P.slice_base + q], 0};
+        hdr_lds[q] = RowHdr{(uint32_t)A.slice_off[P.slice_base + q], A.slice_w[P.slice_base + q]};
+    const Topo<Prec> tpg = topo_of<Prec>(A, P);
     // rows of this wave: i = 0 .. nrow-1 (node i*BLOCK + tid, slice i*NW + wave)
     const int nrow = (N - wave * kWave + BLOCK - 1) / BLOCK;
-    auto hdr_of = [&](int i) -> RowHdr { return hdr_lds[i * NW + wave]; };
-    // stream cursor: row i, first incidence k0 of the chunk; i >= nrow = end
+    auto hdr_of = [&](int i) -> RowHdr { return uniform_hdr(hdr_lds + i * NW + wave); };
+    // stream cursor: row i, first incidence k0 of the chunk, row width w;
+    // i >= nrow = end of the stream
     struct Cur {
-        int i, k0;
+        int i, k0, w;
     };
     auto first_from = [&](int i) -> Cur {
-        while (i < nrow && hdr_of(i).w == 0) ++i;
-        return Cur{i, 0};
+        int w = 0;
+        while (i < nrow && (w = hdr_of(i).w) == 0) ++i;
+        return Cur{i, 0, w};
     };
     auto next = [&](Cur c) -> Cur {
         if (c.i >= nrow) return c;
-        if (c.k0 + C < hdr_of(c.i).w) return Cur{c.i, c.k0 + C};
+        if (c.k0 + C < c.w) return Cur{c.i, c.k0 + C, c.w};
         return first_from(c.i + 1);
     };
     auto topo = [&](Cur c, Cur dummy, Pref<Prec, C> &pf) {
         const Cur x = c.i < nrow ? c : dummy;
-        const RowHdr h = hdr_of(x.i);
-        pref_load<Prec, C>(A, h.e0, h.w, x.k0, lane, pf);
+        pref_load<Prec, C>(tpg, hdr_of(x.i), x.k0, lane, pf);
     };
     auto node_data = [&](int i, NodeData<T> &nd) {
         const int r = i * BLOCK + tid;
@@ -887,10 +925,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         nd.w[0] = nd.w[1] = nd.w[2] = 0;
         nd.im = 0;
         nd.m = 0.0;
-        nd.d = 0;
         if (r < N) {
             pos.load(r, nd.q[0], nd.q[1], nd.q[2]);
-            nd.d = A.deg[nb + r];
             if (r < Nf) {
                 nd.im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
                 nd.m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
@@ -982,7 +1018,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 const Cur c2 = next(c1);
                 topo(c2, cfirst, t1);
                 // stage 3: forces of c0
-                force_pre<C>(k0c, px0, py0, pz0, af, c0.k0, n0.d, n0.q[0], n0.q[1], n0.q[2], g[0],
+                force_pre<C>(k0c, px0, py0, pz0, af, c0.w - c0.k0, n0.q[0], n0.q[1], n0.q[2], g[0],
                              g[1], g[2]);
                 if (!c1_valid || c1_new_row) {
                     // c0 was the last chunk of its row: the node's damped
@@ -1020,11 +1056,13 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 }
             }
         }
-        block_sum3<NW>(red, lane, wave, gf2, gb2, ke2);
+        block_sum2<NW>(red, lane, wave, gf2, gb2);
         ++n;
-        if (stop_test(A, P, tol2, gf2, gb2, ke2, n, status, pg)) break;
+        if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (n - n0 >= A.budget) break;
     }
+    // kinetic energy of the last pass (reported only)
+    ke2 = block_sum1<NW>(red, lane, wave, ke2);
     final_scalars(P, gf2, gb2, ke2, rho, ke);
 
     if (status != kStatusRunning) {
@@ -1197,7 +1235,8 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_force(SolveArgs A, int slot
             gb2 = gg;
         }
     }
-    block_sum3<kLoopBlock / kWave>(red, lane, wave, gf2, gb2, ke2);
+    block_sum2<kLoopBlock / kWave>(red, lane, wave, gf2, gb2);
+    ke2 = block_sum1<kLoopBlock / kWave>(red, lane, wave, ke2);
     if (tid == 0) {
         partial[3 * blockIdx.x + 0] = gf2;
         partial[3 * blockIdx.x + 1] = gb2;

@@ -15,7 +15,12 @@
 // incidences follow ascending fiber id.  Each entry carries the neighbour's
 // local id and the fiber constants: {EA / (2 L^2), L^2} in FP64, and for the
 // FP32 state {dX (the reference vector to the neighbour), EA / (2 L^2)}.
-// Padding entries hold neighbour 0 and zero constants.
+// Padding entries of a node (its degree up to the slice width) hold zero
+// constants and a neighbour at a positive distance (the node's first real
+// neighbour), so they add exactly zero force; lanes past the problem's last
+// node hold neighbour 0 and zero constants.  The L^2 of an incidence is
+// rounded as the kernels form squared lengths, fma(dz, dz, fma(dy, dy,
+// dx * dx)).
 #pragma once
 #include <stdint.h>
 

@@ -263,19 +263,26 @@ def test_all_prescribed_and_max_iter():
 
 
 def test_warm_start_parity():
+    """Cold solve, then a warm solve under F + sym U(0.002), on both sides,
+    each warm-starting from its own cold displacements.  Those differ within
+    the stopping band (u is not unique on floppy networks), so the 1e-8
+    stress bar is checked at tol 1e-10, as for the full batch."""
     batch = I.small_batch(4, 100, 300, 0.02, seed=24)
     rng = np.random.default_rng(5)
     F2 = np.stack([F + (I.sym_perturbed_F(rng, 0.002) - np.eye(3)) for F in batch.F])
     say("warm start: cold solve then warm solve with F + sym U(0.002)")
-    b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
+    tol = 1e-10
+    b = dr.DRBatch(batch, tol=tol, damping=1e-3, dt_safety=S)
     b.solve()
     cold = b.results()
     b.solve(F=F2, start=dr.DR_START_WARM)
     warm = b.results(want_u=True)
     for i in range(len(batch)):
-        o1 = O.solve(batch.nets[i], batch.F[i], tol=1e-8, beta=1e-3, dt_safety=S)
-        o2 = O.solve(batch.nets[i], F2[i], tol=1e-8, beta=1e-3, dt_safety=S, start=O.START_WARM,
+        o1 = O.solve(batch.nets[i], batch.F[i], tol=tol, beta=1e-3, dt_safety=S)
+        o2 = O.solve(batch.nets[i], F2[i], tol=tol, beta=1e-3, dt_safety=S, start=O.START_WARM,
                      F_prev=batch.F[i], u_prev=o1.u)
+        say(f"net {i}: warm passes {int(warm['iters'][i])} (oracle {o2.iters}), sigma rel "
+            f"{rel(warm['sigma'][i], o2.sigma):.2e}")
         assert passes_close(warm["iters"][i], o2.iters)
         assert rel(warm["sigma"][i], o2.sigma) < 1e-8
         assert warm["iters"][i] < cold["iters"][i]
