@@ -137,12 +137,146 @@ def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
     return out
 
 
+def uneven_main(args):
+    """The 1024-network batch with node counts log-uniform in [2000, 33000]:
+    launch shapes tuned per size bucket, the solve step captured in a HIP
+    graph; a step is one graph launch making a fixed number of passes on
+    every network (plus the stress), timed against the untuned default plans.
+    With --converge the batch is then solved to convergence in budgeted
+    launches (progress printed after each)."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import inputs as I
+    from paper_2305_07030_amd import tune as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dr.load()
+    t = time.perf_counter()
+    batch = I.config_uneven_batch(1024)
+    M = np.array([n.n_fibers for n in batch.nets], np.float64)
+    N = np.array([n.n_nodes for n in batch.nets])
+    log(f"generated 1024 networks, {int(N.sum())} nodes, {int(M.sum())} fibers in "
+        f"{time.perf_counter() - t:.1f}s")
+    beta, K = 1e-4, args.passes
+    wl = ("1024 kNN(k=3) fiber networks, N = round(exp U(ln 2000, ln 33000)), "
+          "F = I + sym U(+-0.02), FP64")
+    tuner = T.Tuner(passes=300, reps=1, confirm_passes=K, log=lambda m: log("tune:", m))
+    t = time.perf_counter()
+    plans = tuner.tune(batch)
+    tune_s = time.perf_counter() - t
+    log(f"tuned in {tune_s:.1f}s:", [{k: p[k] for k in ("n_hi", "block", "chunk", "placement")}
+                                     for p in plans])
+    stream = torch.cuda.Stream()
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()  # F is in HBM before the batch stream uses it
+
+    def timed(b, use_graph, label):
+        if use_graph:
+            b.graph_capture(Fd)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for w in range(args.warmup):
+            b.graph_launch() if use_graph else b.solve_device(Fd)
+            b.results()
+            log(f"{label} warmup {w} done")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            b.graph_launch() if use_graph else b.solve_device(Fd)
+            ev[k][1].record(stream)
+            r = b.results()
+            log(f"{label} step {k}: {ev[k][0].elapsed_time(ev[k][1]):.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # every network makes the K passes unless it diverges (NONFINITE) first
+        done = (r["result"] == dr.DR_MAX_ITER) | (r["result"] == dr.DR_NONFINITE)
+        assert done.all() and (r["iters"][r["result"] == dr.DR_MAX_ITER] == K).all()
+        upd = float((M * r["iters"]).sum())
+        kern = sum(a.elapsed_time(e) for a, e in ev) / 1e3 / args.steps
+        return upd * args.steps / wall, wall / args.steps, kern, upd, r
+
+    with torch.cuda.stream(stream):
+        bt = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=beta, dt_safety=0.9,
+                        stream=stream.cuda_stream)
+        T.apply(bt, plans)
+        classes = bt.classes()
+        v_tuned, step_s, kern_s, upd, r = timed(bt, True, "tuned+graph")
+        bt.close()
+        bd = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=beta, dt_safety=0.9,
+                        stream=stream.cuda_stream)
+        default_classes = bd.classes()
+        v_default, dstep_s, _, _, _ = timed(bd, False, "default")
+        bd.close()
+    n_div = int((r["result"] == dr.DR_NONFINITE).sum())
+    out = {
+        "metric": "fiber-element updates/s (batched persistent launch, fixed pass count)",
+        "value": v_tuned, "unit": "fiber-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl, "networks": 1024, "nodes": int(N.sum()), "fibers": int(M.sum()),
+                   "passes_per_step": K, "diverged_before_K": n_div, "damping": beta,
+                   "dt_safety": 0.9,
+                   "plans": [{k: p[k] for k in ("n_hi", "block", "chunk", "placement")} for p in plans],
+                   "classes": classes, "tuning_s": tune_s},
+        "default_plans": {"value": v_default, "ms_per_step": dstep_s * 1e3,
+                          "classes": default_classes},
+        "roofline": {"bound": "hbm", "achieved": BYTES_PER_UPDATE * upd / kern_s / 1e9,
+                     "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": BYTES_PER_UPDATE * upd / kern_s / PEAK_HBM, "traffic": None,
+                     "kernel": "k_dr_glb (the networks above the LDS limit carry most fibers)",
+                     "kernel_ms": kern_s * 1e3, "bytes_per_update": BYTES_PER_UPDATE},
+    }
+    if args.converge:
+        out["converge"] = uneven_converge(batch, plans, beta, M, args.converge_limit)
+    print(json.dumps(out), flush=True)
+
+
+def uneven_converge(batch, plans, beta, M, limit_s):
+    """Every network to tol 1e-8 (max 2e6 passes) in launches of at most
+    100 000 passes each; the total wall time includes the host round trips."""
+    import numpy as np
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import tune as T
+    b = dr.DRBatch(batch, tol=1e-8, max_iter=2_000_000, damping=beta, dt_safety=0.9)
+    T.apply(b, plans)
+    ids = np.arange(len(batch), dtype=np.int32)
+    t0 = time.perf_counter()
+    b.advance(ids, np.full(len(ids), dr.DR_START_AFFINE, np.int32), 100_000, F=batch.F)
+    while True:
+        q = b.query(ids)
+        run = ids[q["result"] == dr.DR_RUNNING]
+        el = time.perf_counter() - t0
+        log(f"converge: {el:.1f}s, running {len(run)}, passes max {int(q['iters'].max())}")
+        if len(run) == 0 or el > limit_s:
+            break
+        b.advance(run, np.full(len(run), dr.DR_RESUME, np.int32), 100_000)
+    wall = time.perf_counter() - t0
+    it = q["iters"]
+    b.close()
+    return {"wall_s": wall, "updates": float((M * it).sum()),
+            "value": float((M * it).sum()) / wall, "unit": "fiber-updates/s",
+            "status_counts": {name: int((q["result"] == code).sum()) for name, code in
+                              (("converged", dr.DR_CONVERGED), ("max_iter", dr.DR_MAX_ITER),
+                               ("nonfinite", dr.DR_NONFINITE), ("running", dr.DR_RUNNING))},
+            "passes_median": int(np.median(it)), "passes_max": int(it.max()),
+            "time_limit_s": limit_s}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "single"])
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "single", "uneven"])
+    ap.add_argument("--passes", type=int, default=20000,
+                    help="uneven workload: passes per network per step")
+    ap.add_argument("--converge", action="store_true",
+                    help="uneven workload: also solve the batch to convergence")
+    ap.add_argument("--converge-limit", type=float, default=900.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--placement", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -155,6 +289,9 @@ def main():
               "(the sub-problems are independent; see the design notes on sharding).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "uneven":
+        return uneven_main(args)
 
     import numpy as np
     import torch

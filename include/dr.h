@@ -266,7 +266,7 @@ dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_f
  * chunk, placement) used for every solve of the batch, and the classes of a
  * launch run concurrently on internal streams.  By default: the largest set
  * of problems the LDS / register variant can hold, then the rest in global
- * placement.  A problem's result depends only on its class's shape, not on
+ * placement.  A problem's result depends neither on its class's shape nor on
  * which other problems share a launch.  Classes that would hold no problem
  * of the batch are dropped, so every listed class has n_problems > 0.
  *
@@ -283,9 +283,11 @@ dr_status dr_batch_class_info(const dr_batch *b, int32_t c, int32_t *n_classes, 
  * Replaces the size classes (the autotuner's entry point): class k covers the
  * node counts (n_hi[k-1], n_hi[k]] with the given block (0/256/512/1024),
  * chunk (0/1/2/4) and placement (dr_placement); problems above n_hi[n-1] get the
- * automatic split.  n_hi must increase.  Only before the first solve of the
- * batch (DR_E_STATE afterwards); DR_E_INVALID when a DR_PLACE_LDS class
- * cannot hold its largest problem.
+ * automatic split.  n_hi must increase.  Every launch shape computes the
+ * same per-node arithmetic in the same order, so results do not depend on
+ * the plans and they may be changed at any time: the call waits for the
+ * batch's queued work and drops a graph captured with dr_graph_capture.
+ * DR_E_INVALID when a DR_PLACE_LDS class cannot hold its largest problem.
  */
 dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi,
                              const int32_t *block, const int32_t *chunk, const int32_t *placement);

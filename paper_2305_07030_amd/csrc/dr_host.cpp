@@ -100,11 +100,11 @@ struct dr_batch {
     // last dr_solve* call
     int32_t last_n = -1;
     std::vector<int32_t> last_ids;
-    // Size classes: each class has one launch shape, fixed before the first
-    // solve, so a problem's arithmetic -- and its result, bit for bit --
-    // depends only on its size class, not on which problems share a launch.
-    // Classes are launched concurrently on their own streams (fork / join on
-    // the batch stream).
+    // Size classes: each class has one launch shape.  Every shape computes
+    // the same per-node arithmetic in the same order, so a problem's result
+    // is the same, bit for bit, whatever its class's shape and whichever
+    // problems share a launch.  Classes are launched concurrently on their
+    // own streams (fork / join on the batch stream).
     struct Class {
         int32_t n_lo = 0, n_hi = 0; // node counts covered (inclusive)
         int32_t n_max = 0;          // largest problem of the batch in the class
@@ -118,7 +118,6 @@ struct dr_batch {
     std::vector<int32_t> slot_count;    // per class, slots of the staged launch
     std::vector<int32_t> slot_off;      // per class, first entry in the slot order
     hipEvent_t fork = nullptr;
-    bool solved_once = false;
     // captured solve step
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -810,7 +809,6 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
         if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
         return DR_OK;
     };
-    b->solved_once = true;
     if (used == 1) return one((size_t)only, b->stream);
     HIPCHECK(hipEventRecord(b->fork, b->stream));
     for (size_t c = 0; c < b->classes.size(); ++c) {
@@ -1137,8 +1135,6 @@ dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi
     try {
         g_err.clear();
         if (!b) return fail(DR_E_INVALID, "batch is NULL");
-        if (b->solved_once)
-            return fail(DR_E_STATE, "class plans must be set before the first solve of the batch");
         if (n_classes < 0 || n_classes > 16) return fail(DR_E_INVALID, "n_classes must be in [0, 16]");
         if (n_classes > 0 && (!n_hi || !block || !chunk || !placement))
             return fail(DR_E_INVALID, "a class-plan array is NULL");
@@ -1155,6 +1151,12 @@ dr_status dr_set_class_plans(dr_batch *b, int32_t n_classes, const int32_t *n_hi
                 return fail(DR_E_INVALID, "placement of class %d is not a dr_placement value", k);
             req.push_back(ClassRequest{n_hi[k], block[k], chunk[k], placement[k]});
         }
+        // Launch shapes do not change results, so plans may change between
+        // solves: wait for the batch's work (the class streams join it), and
+        // drop a captured graph, which holds the old shapes.
+        HIPCHECK(hipStreamSynchronize(b->stream));
+        if (b->graph_exec) { (void)hipGraphExecDestroy(b->graph_exec); b->graph_exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
         return build_classes(b, req);
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_set_class_plans");

@@ -2,19 +2,30 @@
 
 The paper runs every sub-problem with one fixed team size (section IV); on
 gfx950 the best shape depends on the node count: how many nodes each lane
-holds, whether the nodal state fits in LDS, and how many workgroups share a
-compute unit.  The tuner splits a batch's node-count range into buckets,
-times every valid plan (block, chunk, placement) on a sample of each bucket's
-own problems at a fixed pass count, and hands the fastest plan per bucket to
-dr_set_class_plans before the batch's first solve.
+holds, whether the nodal state fits in LDS, how far ahead the gather loads,
+and how many workgroups share a compute unit.  The tuner splits a batch's
+node-count range into buckets and picks one plan (block, chunk, placement)
+per bucket for dr_set_class_plans.
 
-What is timed is one launch over the sample, all problems at the same pass
-count, so a plan's score carries both its per-pass latency and how many of
-its workgroups fit on a compute unit at once.  Only the launch shape changes
-between candidates: every plan computes the same iteration.
+Plans are scored on the whole batch, because the size classes of a launch
+run concurrently and compete for compute units and memory bandwidth: a plan
+that is fastest for a bucket alone can slow the batch down.  Starting from
+the library's automatic plans, the tuner visits the buckets in order of the
+fibers they carry and, for each, keeps the candidate that shortens a
+fixed-pass launch of the whole batch by at least 2 %.  The result is then
+confirmed against the library's default split (no plans: one class for the
+LDS-resident sizes, one for the rest) on launches of the pass count the
+plans are for (by default ten times the search's: short launches overweight
+set-up, and how the classes' workgroups fall into rounds on the compute
+units changes with the launch length) and kept only if it is faster there
+too; otherwise the tuner returns no plans.  Every launch shape
+computes the same per-node arithmetic in the same order, so a candidate must
+also reproduce the incumbent's pass counts exactly; one that does not is
+rejected.
 
 Results are cached in memory and, if a path is given, in a JSON file keyed by
-device architecture, compute-unit count, precision and bucket bounds.
+device architecture, compute-unit count, precision, pass count and the
+batch's bucket histogram.
 """
 from __future__ import annotations
 
@@ -38,12 +49,15 @@ CHUNKS = (1, 2, 4)
 
 @dataclass(frozen=True)
 class Plan:
-    block: int
-    chunk: int
-    placement: int
+    block: int      # 0 = automatic
+    chunk: int      # 0 = automatic
+    placement: int  # a dr_placement value
 
     def as_dict(self, n_hi: int) -> dict:
         return dict(n_hi=int(n_hi), block=self.block, chunk=self.chunk, placement=self.placement)
+
+
+AUTO = Plan(0, 0, dr.DR_PLACE_AUTO)
 
 
 def buckets(sizes: Sequence[int], edges: Sequence[int] = DEFAULT_EDGES) -> List[Tuple[int, int, np.ndarray]]:
@@ -69,18 +83,10 @@ def candidates(n_max: int) -> List[Plan]:
             continue  # more lanes than twice the nodes: idle lanes only
         for ch in CHUNKS:
             out.append(Plan(blk, ch, dr.DR_PLACE_LDS))
-        out.append(Plan(blk, 4, dr.DR_PLACE_GLOBAL))
+        # global placement with 256 lanes runs chunks of 1 only
+        for ch in ((1,) if blk == 256 else CHUNKS):
+            out.append(Plan(blk, ch, dr.DR_PLACE_GLOBAL))
     return out
-
-
-def sample(sizes: np.ndarray, idx: np.ndarray, k: int) -> np.ndarray:
-    """Up to k members of a bucket spread over its size range, always
-    including its largest problem."""
-    if len(idx) <= k:
-        return idx
-    order = idx[np.argsort(sizes[idx], kind="stable")]
-    pick = np.unique(np.linspace(0, len(order) - 1, k).round().astype(int))
-    return order[pick]
 
 
 def device_key(precision: int) -> str:
@@ -89,47 +95,57 @@ def device_key(precision: int) -> str:
     return f"{getattr(p, 'gcnArchName', p.name)}|cu{p.multi_processor_count}|prec{precision}"
 
 
-def time_plan(sub, plan: Plan, *, passes: int, precision: int, reps: int,
-              clock: Callable[[], float] = time.perf_counter) -> Optional[float]:
-    """Median wall time of one fixed-pass launch over the sub-batch with this
-    plan, or None when the library rejects the plan for it or a problem of the
-    sample does not complete the passes."""
-    n_hi = max(n.n_nodes for n in sub.nets)
-    b = dr.DRBatch(sub, tol=1e-300, max_iter=passes, precision=precision)
-    try:
+class BatchTimer:
+    """Times launches of one batch, every problem started afresh and run for
+    a fixed number of passes, under given class plans."""
+
+    def __init__(self, batch, *, precision: int, reps: int,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.batch = batch
+        self.b = dr.DRBatch(batch, tol=1e-300, max_iter=2 ** 62, precision=precision)
+        self.ids = np.arange(len(batch), dtype=np.int32)
+        self.starts = np.full(len(batch), dr.DR_START_AFFINE, np.int32)
+        self.reps = reps
+        self.clock = clock
+
+    def _launch(self, passes: int):
+        self.b.advance(self.ids, self.starts, passes, F=self.batch.F)
+        self.b.sync()
+
+    def __call__(self, plans: List[dict], passes: int) -> Optional[Tuple[float, np.ndarray]]:
+        """(median seconds per launch, pass counts), or None when the library
+        rejects the plans."""
         try:
-            b.set_class_plans([plan.as_dict(n_hi)])
+            self.b.set_class_plans(plans)
         except dr.DrError as e:
             if e.status == dr.DR_E_INVALID:
                 return None
             raise
-        b.solve()
-        b.sync()  # warm-up
-        # a plan must run the sample's passes to the end (no early stop)
-        if not (b.results()["result"] == dr.DR_MAX_ITER).all():
-            return None
+        self._launch(passes)  # warm-up (loads the shapes' kernels)
         ts = []
-        for _ in range(reps):
-            t0 = clock()
-            b.solve()
-            b.sync()
-            ts.append(clock() - t0)
-        return float(np.median(ts))
-    finally:
-        b.close()
+        for _ in range(self.reps):
+            t0 = self.clock()
+            self._launch(passes)
+            ts.append(self.clock() - t0)
+        return float(np.median(ts)), self.b.query(self.ids)["iters"].copy()
+
+    def close(self):
+        self.b.close()
 
 
 class Tuner:
-    def __init__(self, *, edges: Sequence[int] = DEFAULT_EDGES, passes: int = 1000,
-                 sample_size: int = 64, reps: int = 3, cache_path: Optional[str] = None,
-                 timer: Callable = time_plan, key: Optional[Callable[[int], str]] = None,
+    def __init__(self, *, edges: Sequence[int] = DEFAULT_EDGES, passes: int = 300, reps: int = 1,
+                 confirm_passes: Optional[int] = None, cache_path: Optional[str] = None,
+                 timer_factory: Optional[Callable] = None,
+                 key: Optional[Callable[[int], str]] = None,
                  log: Callable[[str], None] = lambda s: None):
         self.edges = tuple(edges)
         self.passes = int(passes)
-        self.sample_size = int(sample_size)
+        self.confirm_passes = int(confirm_passes or 10 * passes)
         self.reps = int(reps)
         self.cache_path = cache_path
-        self.timer = timer
+        self.timer_factory = timer_factory or (
+            lambda batch, precision: BatchTimer(batch, precision=precision, reps=self.reps))
         self.key = key or device_key
         self.log = log
         self.cache: Dict[str, dict] = {}
@@ -146,34 +162,62 @@ class Tuner:
             os.replace(tmp, self.cache_path)
 
     def tune(self, batch, precision: int = dr.DR_FP64) -> List[dict]:
-        """Class plans (ascending n_hi) for dr_set_class_plans; each entry also
-        carries the bucket's measured times under 'times'."""
+        """Class plans (ascending n_hi) for dr_set_class_plans; block, chunk
+        and placement 0 mean the library's automatic choice; an empty list
+        keeps the library's default split."""
         sizes = np.array([n.n_nodes for n in batch.nets])
-        dkey = self.key(precision)
-        plans = []
-        for lo, hi, idx in buckets(sizes, self.edges):
-            ckey = f"{dkey}|{lo}-{hi}|K{self.passes}"
-            if ckey not in self.cache:
-                sub = batch.subset(sample(sizes, idx, self.sample_size))
-                n_max = int(sizes[idx].max())
-                times = {}
-                for pl in candidates(n_max):
-                    t = self.timer(sub, pl, passes=self.passes, precision=precision, reps=self.reps)
-                    if t is not None:
-                        times[f"{pl.block}/{pl.chunk}/{pl.placement}"] = t
-                        self.log(f"bucket ({lo},{hi}] n={len(sub)} plan {pl}: {t * 1e3:.3f} ms")
-                if not times:
-                    raise dr.DrError(dr.DR_E_INVALID, f"no valid plan for bucket ({lo},{hi}]")
-                best = min(times, key=times.get)
-                self.cache[ckey] = dict(best=best, times=times, sample=len(sub))
-                self._save()
-            ent = self.cache[ckey]
-            blk, ch, place = (int(x) for x in ent["best"].split("/"))
-            plans.append(dict(n_hi=int(hi), block=blk, chunk=ch, placement=place,
-                              times=dict(ent["times"])))
-        return plans
+        fibers = np.array([n.n_fibers for n in batch.nets])
+        bks = buckets(sizes, self.edges)
+        ckey = (f"{self.key(precision)}|K{self.passes}/{self.confirm_passes}|" +
+                ",".join(f"{lo}-{hi}:{len(idx)}" for lo, hi, idx in bks))
+        if ckey in self.cache:
+            return [dict(p) for p in self.cache[ckey]["plans"]]
+        timer = self.timer_factory(batch, precision)
+        try:
+            his = [hi for _, hi, _ in bks]
+            cur = [AUTO] * len(bks)
+
+            def as_plans(pl):
+                return [p.as_dict(h) for p, h in zip(pl, his)]
+            res = timer(as_plans(cur), self.passes)
+            if res is None:
+                raise dr.DrError(dr.DR_E_INVALID, "the automatic plans were rejected")
+            t_best, iters_ref = res
+            t_auto = t_best
+            self.log(f"automatic plans: {t_best * 1e3:.2f} ms")
+            order = sorted(range(len(bks)), key=lambda k: -int(fibers[bks[k][2]].sum()))
+            for k in order:
+                lo, hi, idx = bks[k]
+                for cand in candidates(int(sizes[idx].max())):
+                    trial = list(cur)
+                    trial[k] = cand
+                    res = timer(as_plans(trial), self.passes)
+                    if res is None:
+                        continue
+                    t, iters = res
+                    if not np.array_equal(iters, iters_ref):
+                        self.log(f"bucket ({lo},{hi}] {cand}: pass counts differ, rejected")
+                        continue
+                    self.log(f"bucket ({lo},{hi}] {cand}: {t * 1e3:.2f} ms")
+                    if t < 0.98 * t_best:
+                        cur, t_best = trial, t
+            plans = as_plans(cur)
+            long = self.confirm_passes
+            t_tuned = timer(plans, long)[0]
+            t_default = timer([], long)[0]
+            confirm = dict(passes=long, ms_tuned=t_tuned * 1e3, ms_default=t_default * 1e3)
+            self.log(f"confirm at {long} passes: tuned {t_tuned * 1e3:.1f} ms, default split "
+                     f"{t_default * 1e3:.1f} ms")
+            if not t_tuned < 0.98 * t_default:
+                plans = []
+            self.cache[ckey] = dict(plans=plans, ms=t_best * 1e3, ms_automatic=t_auto * 1e3,
+                                    confirm=confirm)
+            self._save()
+            return [dict(p) for p in plans]
+        finally:
+            timer.close()
 
 
 def apply(b: "dr.DRBatch", plans: List[dict]):
-    """Install tuned class plans on a batch (before its first solve)."""
+    """Install tuned class plans on a batch."""
     b.set_class_plans([{k: p[k] for k in ("n_hi", "block", "chunk", "placement")} for p in plans])

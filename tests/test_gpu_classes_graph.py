@@ -91,8 +91,14 @@ def test_class_plan_override():
     o = oracle_fixed(batch, K, 1e-3)
     for i, (oi, su, ss) in enumerate(o):
         assert rel(g["sigma"][i], oi.sigma) < 1e-12 + 100 * ss
-    with pytest.raises(dr.DrError):
-        b.set_class_plans([dict(n_hi=500, block=256, chunk=4, placement=dr.DR_PLACE_LDS)])
+    # plans may change between solves; the results do not depend on them
+    b.set_class_plans([dict(n_hi=9000, block=512, chunk=1, placement=dr.DR_PLACE_GLOBAL)])
+    assert [c["n_problems"] for c in b.classes()] == [5]
+    b.solve()
+    g2 = b.results()
+    assert np.array_equal(g2["sigma"], g["sigma"]) and np.array_equal(g2["iters"], g["iters"])
+    with pytest.raises(dr.DrError):  # LDS cannot hold 8000 nodes
+        b.set_class_plans([dict(n_hi=9000, block=1024, chunk=1, placement=dr.DR_PLACE_LDS)])
 
 
 def test_graph_replay_equals_eager():
@@ -118,6 +124,10 @@ def test_graph_replay_equals_eager():
         # an eager solve after the replays is unchanged too
         b.solve_device(Fd)
         assert np.array_equal(b.results()["sigma"], eager["sigma"])
+        # new plans drop the captured graph
+        b.set_class_plans([dict(n_hi=1000, block=256, chunk=1, placement=dr.DR_PLACE_GLOBAL)])
+        with pytest.raises(dr.DrError):
+            b.graph_launch()
     torch.cuda.synchronize()
 
 
@@ -127,14 +137,15 @@ def test_tuned_plans_apply_and_match_oracle(tmp_path):
     sizes = [120, 200, 350, 480, 700, 900, 1500, 2600]
     nets = [I.draw_network(rng, n) for n in sizes]
     batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
-    tu = T.Tuner(edges=(256, 1024), passes=200, sample_size=4, reps=1,
+    tu = T.Tuner(edges=(256, 1024), passes=200, reps=1,
                  cache_path=str(tmp_path / "tune.json"), log=say)
     plans = tu.tune(batch)
     say("tuned", [{k: p[k] for k in ("n_hi", "block", "chunk", "placement")} for p in plans])
-    assert [p["n_hi"] for p in plans] == [256, 1024, 2600]
+    assert [p["n_hi"] for p in plans] in ([256, 1024, 2600], [])  # [] = default split won
     b = dr.DRBatch(batch, tol=1e-8, damping=1e-3, dt_safety=S)
     T.apply(b, plans)
-    assert [c["n_problems"] for c in b.classes()] == [2, 4, 2]
+    if plans:
+        assert [c["n_problems"] for c in b.classes()] == [2, 4, 2]
     b.solve()
     g = b.results()
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
