@@ -36,6 +36,29 @@ BYTES_PER_UPDATE = 104.0
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_HBM = 8.0e12
 
+# Bytes one launch moves beyond L2 (HBM and Infinity Cache), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs of this benchmark scaled by what the same
+# counters read for a plain copy of known size (profiles/ holds the summary
+# and the commands).  Valid only for the kernel source it was measured on:
+# any change to the kernels makes the figure null until it is measured again.
+MEASURED_TRAFFIC = {
+    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7242067016.1 KiB x 1.9997 + WRITE 18354.5 KiB x 1.0
+    "uniform": {"kernels": "d95c0f05c94edc6f", "bytes_per_launch": 1.4829460e13},
+}
+
+
+def kernels_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2305_07030_amd", "csrc", "dr_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(workload):
+    t = MEASURED_TRAFFIC.get(workload)
+    if t is None or t["kernels"] != kernels_digest():
+        return None
+    return t["bytes_per_launch"]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -283,6 +306,8 @@ def main():
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -308,6 +333,13 @@ def main():
         batch, beta, tol = I.config_single(), 1e-3, 1e-8
         wl = "1 kNN(k=3) fiber network, N = 500, F = diag(1.01,1,1), FP64, tol 1e-8"
     log("workload:", wl, "networks", len(batch), "fibers", batch.total_fibers)
+    if args.copy_mib:
+        x = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)  # reads and writes copy_mib MiB once each
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
+        del x, y
     stream = torch.cuda.current_stream()
     b = dr.DRBatch(batch, tol=tol, damping=beta, dt_safety=0.9, block=args.block,
                    placement=args.placement, stream=stream.cuda_stream)
@@ -360,7 +392,8 @@ def main():
                    "passes_min": int(r["iters"].min()), "passes_max": int(r["iters"].max()),
                    "passes_median": int(np.median(r["iters"])), "converged": n_conv},
         "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / PEAK_FP64_VECTOR, "traffic": None,
+                     "unit": "TFLOP/s", "frac": flops / PEAK_FP64_VECTOR,
+                     "traffic": traffic_for(args.workload),
                      "kernel": "k_dr_reg" if info["nodes_per_thread"] > 0 else "k_dr_glb",
                      "kernel_ms": kern_s * 1e3,
                      "flop_per_update": FLOP_PER_UPDATE,
