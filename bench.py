@@ -92,17 +92,29 @@ def cpu_baseline(batch, beta, tol, target_s=15.0):
                       f"(fixed pass count), one network per thread, {wall:.1f}s wall"}
 
 
-def fp32_leg(batch, beta, r64, M, stream):
-    """The same batch with FP32 nodal state and force gather (FP64 norms and
-    stress), tol 1e-6 with a 50 000-pass stall guard; stress error per network
-    against this FP64 solve (itself within 1e-7 of the FP64 oracle)."""
+def fp32_leg(batch, stream, beta=1e-3):
+    """The same networks with FP32 nodal state and force gather (FP64 norms
+    and stress), tol 1e-6 with a 50 000-pass stall guard, against an FP64
+    solve of the same iteration (same damping, tol 1e-8).  FP32 rounding is
+    re-injected every pass and amplified by the lightly damped modes (about
+    1/sqrt(beta/2)), so this workload runs at beta = 1e-3, which keeps that
+    floor below the tolerance's scale; the FP64 workload's 1e-4 would leave
+    it near rho ~ 1e-3."""
     import numpy as np
     import torch
 
     from paper_2305_07030_amd import dr
+    M = np.array([n.n_fibers for n in batch.nets], np.float64)
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    b64 = dr.DRBatch(batch, tol=1e-8, damping=beta, dt_safety=0.9, stream=stream.cuda_stream)
+    t = time.perf_counter()
+    b64.solve_device(Fd)
+    r64 = b64.results()
+    wall64 = time.perf_counter() - t
+    b64.close()
     b = dr.DRBatch(batch, tol=1e-6, damping=beta, dt_safety=0.9, precision=dr.DR_FP32,
                    stall_window=50_000, stream=stream.cuda_stream)
-    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
     b.solve_device(Fd)
     b.results()
     torch.cuda.synchronize()
@@ -115,11 +127,15 @@ def fp32_leg(batch, beta, r64, M, stream):
     err = np.linalg.norm(s32 - s64, axis=1) / np.linalg.norm(s64, axis=1)
     upd = float((M * r["iters"]).sum())
     b.close()
-    return {"value": upd / wall, "unit": "fiber-updates/s", "wall_s": wall,
+    return {"value": upd / wall, "unit": "fiber-updates/s", "wall_s": wall, "damping": beta,
             "converged": int((r["result"] == dr.DR_CONVERGED).sum()),
             "stalled": int((r["result"] == dr.DR_STALLED).sum()),
             "rho_median": float(np.median(r["rho"])), "rho_max": float(r["rho"].max()),
             "passes_median": int(np.median(r["iters"])), "passes_max": int(r["iters"].max()),
+            "fp64_reference": {"wall_s": wall64, "tol": 1e-8,
+                               "converged": int((r64["result"] == dr.DR_CONVERGED).sum()),
+                               "passes_median": int(np.median(r64["iters"])),
+                               "passes_max": int(r64["iters"].max())},
             "sigma_rel_err_vs_fp64": {"median": float(np.median(err)),
                                       "p99": float(np.percentile(err, 99)),
                                       "max": float(err.max())},
@@ -420,7 +436,7 @@ def main():
         lb.close()
         log("loop baseline:", out["loop_baseline"])
     if not args.no_fp32 and args.workload == "uniform":
-        out["fp32"] = fp32_leg(batch, beta, r, M, stream)
+        out["fp32"] = fp32_leg(batch, stream)
         log("fp32:", {k: v for k, v in out["fp32"].items() if k != "per_network_sigma_rel_err"})
     if not args.no_serve and args.workload == "uniform":
         out["serving"] = serving_leg(batch, beta)
