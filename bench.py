@@ -142,6 +142,33 @@ def fp32_leg(batch, stream, beta=1e-3):
             "per_network_sigma_rel_err": [float(x) for x in err]}
 
 
+def multistream_leg(batch, beta, n_nets=16, passes=20000):
+    """The per-problem launch loop run by 1, 4 and 16 host threads, each on its
+    own stream (the multi-process-service comparison of the paper, section
+    IV): the first n_nets networks, a fixed pass count each."""
+    from paper_2305_07030_amd import compare as CMP
+    sub = batch.subset(range(n_nets))
+    out = {"sample": f"first {n_nets} networks, {passes} passes each (fixed pass count)",
+           "unit": "fiber-updates/s"}
+    for n in (1, 4, 16):
+        r = CMP.multistream_loop(sub, n, tol=1e-300, max_iter=passes, damping=beta, dt_safety=0.9)
+        out[f"streams_{n}"] = r["updates_per_s"]
+        log(f"loop on {n} streams: {r['updates_per_s']:.3e} updates/s ({r['wall_s']:.2f}s)")
+    # the paper's zero + atomic-scatter force kernel in the same loop, one network
+    from paper_2305_07030_amd import dr
+    one = batch.subset([0])
+    for scatter in (False, True):
+        b = dr.DRBatch(one, tol=1e-300, max_iter=passes, damping=beta, dt_safety=0.9)
+        t = time.perf_counter()
+        b.solve_loop(scatter=scatter)
+        b.results()
+        wall = time.perf_counter() - t
+        b.close()
+        out["scatter_us_per_pass" if scatter else "gather_us_per_pass"] = wall / passes * 1e6
+    log("loop pass times (us): gather", out["gather_us_per_pass"], "scatter", out["scatter_us_per_pass"])
+    return out
+
+
 def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
     """Continuous batching over the resident batch as the pool (FP64): a
     closed-loop run gives the saturated solve rate; open-loop Poisson arrivals
@@ -435,6 +462,9 @@ def main():
                                 "speedup_batched_over_loop": value / (lupd / lw)}
         lb.close()
         log("loop baseline:", out["loop_baseline"])
+    if not args.no_loop and args.workload == "uniform":
+        out["loop_multistream"] = multistream_leg(batch, beta)
+        log("loop multistream:", out["loop_multistream"])
     if not args.no_fp32 and args.workload == "uniform":
         out["fp32"] = fp32_leg(batch, stream)
         log("fp32:", {k: v for k, v in out["fp32"].items() if k != "per_network_sigma_rel_err"})

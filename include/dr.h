@@ -247,6 +247,18 @@ dr_status dr_sync(dr_batch *b);
 dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids,
                         int32_t n_ids, int32_t start);
 
+/*
+ * As dr_solve_loop, with the paper's own force kernel (section III): the
+ * nodal forces are zeroed each pass and every fiber, evaluated once, adds
+ * its force to both ends with FP64 atomic additions.  The order of those
+ * additions varies from run to run, so results agree with dr_solve_loop to
+ * round-off and are not bitwise reproducible.  Comparator only, FP64 only;
+ * the first call allocates a force buffer of 32 B per node of the largest
+ * problem (DR_E_DEVICE if that fails).
+ */
+dr_status dr_solve_loop_scatter(dr_batch *b, const double *F, const int32_t *ids,
+                                int32_t n_ids, int32_t start);
+
 /* Information about the packed batch and the launch chosen for it.
  *   n_problems, total_nodes, total_fibers, block (threads per workgroup),
  *   lds_bytes (dynamic LDS per workgroup), nodes_per_thread. Any may be NULL. */

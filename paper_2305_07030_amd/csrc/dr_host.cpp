@@ -90,6 +90,7 @@ struct dr_batch {
     double *d_F = nullptr;
     int32_t *d_ids = nullptr, *d_order = nullptr, *d_starts = nullptr;
     double *d_partial = nullptr, *d_scalars = nullptr;
+    double *d_gscat = nullptr; // forces of the atomic-scatter comparator (allocated on first use)
     // pinned staging
     double *h_F = nullptr;
     int32_t *h_ids = nullptr, *h_order = nullptr, *h_starts = nullptr;
@@ -132,7 +133,7 @@ void free_all(dr_batch *b)
                    b->d_slice_w, b->d_nbr, b->d_slice_off, b->d_kl, b->d_kl32, b->d_u, b->d_qbuf,
                    b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
-                   b->d_starts, b->d_partial, b->d_scalars};
+                   b->d_starts, b->d_partial, b->d_scalars, b->d_gscat};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars};
@@ -1030,8 +1031,13 @@ dr_status dr_stress(dr_batch *b, double *sigma, double *sigma_fib, double *u, in
     }
 }
 
-dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
-                        int32_t start)
+namespace {
+
+// The per-problem launch loop: one problem after the other, a few kernels per
+// pass and the stop test on the host.  scatter: forces by the zero + atomic
+// scatter kernel instead of the deterministic gather.
+dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
+                     int32_t start, bool scatter)
 {
     try {
         g_err.clear();
@@ -1044,6 +1050,8 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
         if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
         for (int32_t k = 0; k < n_ids; ++k)
             if ((s = check_F(F, k)) != DR_OK) return s;
+        if (scatter && !b->d_gscat)
+            HIPCHECK(hipMalloc(&b->d_gscat, sizeof(double) * 4 * (size_t)std::max(b->n_max, 1)));
         if ((s = stage(b, F, ids, nullptr, n_ids)) != DR_OK) return s;
         SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
         a.order = nullptr;
@@ -1051,14 +1059,14 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
         for (int32_t slot = 0; slot < n_ids; ++slot) {
             const ProbDesc &d = b->desc[b->h_ids[slot]];
             int rc = drk::launch_loop_kernels(a, slot, 0, d.N, b->d_partial, b->d_scalars, 0, 0.0,
-                                              0.0, 0, st);
+                                              0.0, 0, b->d_gscat, st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop set-up launch failed: %s", drk::kernel_error_string(rc));
             int64_t n = 0;
             double rho = 0.0, ke = 0.0;
             int status = DR_MAX_ITER;
             for (;;) {
-                rc = drk::launch_loop_kernels(a, slot, 1, d.N, b->d_partial, b->d_scalars, n, 0.0,
-                                              0.0, 0, st);
+                rc = drk::launch_loop_kernels(a, slot, scatter ? 3 : 1, d.N, b->d_partial,
+                                              b->d_scalars, n, 0.0, 0.0, 0, b->d_gscat, st);
                 if (rc != 0) return fail(DR_E_DEVICE, "loop pass launch failed: %s", drk::kernel_error_string(rc));
                 HIPCHECK(hipMemcpyAsync(b->h_scalars, b->d_scalars, 3 * sizeof(double),
                                         hipMemcpyDeviceToHost, st));
@@ -1073,7 +1081,7 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
                 if (n >= b->opt.max_iter) { status = DR_MAX_ITER; break; }
             }
             rc = drk::launch_loop_kernels(a, slot, 2, d.N, b->d_partial, b->d_scalars, n, rho, ke,
-                                          status, st);
+                                          status, b->d_gscat, st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop stress launch failed: %s", drk::kernel_error_string(rc));
             b->running[b->h_ids[slot]] = 0;
         }
@@ -1085,6 +1093,20 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_solve_loop");
     }
+}
+
+} // namespace
+
+dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
+                        int32_t start)
+{
+    return solve_loop(b, F, ids, n_ids, start, false);
+}
+
+dr_status dr_solve_loop_scatter(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
+                                int32_t start)
+{
+    return solve_loop(b, F, ids, n_ids, start, true);
 }
 
 dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_nodes,

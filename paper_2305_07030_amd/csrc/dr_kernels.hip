@@ -1244,6 +1244,97 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_force(SolveArgs A, int slot
     }
 }
 
+// The paper's force kernel (section III) for the launch-loop comparator:
+// forces zeroed, then every fiber evaluated once, from the incidences of its
+// lower-numbered end, and added to both ends with FP64 atomics.  The
+// summation order depends on the timing of the atomics, so results vary at
+// round-off from run to run.
+__global__ void __launch_bounds__(kLoopBlock) k_loop_zero(SolveArgs A, int slot, double *g)
+{
+    const int p = A.ids ? A.ids[slot] : slot;
+    const int r = blockIdx.x * kLoopBlock + threadIdx.x;
+    if (r < A.probs[p].N) {
+        g[4 * r + 0] = 0.0;
+        g[4 * r + 1] = 0.0;
+        g[4 * r + 2] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kLoopBlock) k_loop_scatter(SolveArgs A, int slot, double *g)
+{
+    const int p = A.ids ? A.ids[slot] : slot;
+    const ProbDesc P = A.probs[p];
+    const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int r = blockIdx.x * kLoopBlock + tid;
+    const int wbase = blockIdx.x * kLoopBlock + wave * kWave;
+    if (wbase >= P.N) return;
+    const Row row = node_row(A, P, wbase);
+    if (r >= P.N) return;
+    double xi, yi, zi;
+    pos.load(r, xi, yi, zi);
+    const int d = A.deg[P.node_base + r];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const int64_t e = row.e0 + (int64_t)k * kWave + lane;
+        const int j = A.nbr[e];
+        if (j < r) continue; // the other end evaluates this fiber
+        const KL c = A.kl[e];
+        double dx, dy, dz;
+        pos.load(j, dx, dy, dz);
+        dx -= xi; dy -= yi; dz -= zi;
+        const double l2 = len2(dx, dy, dz);
+        const double s = c.k * (l2 - c.L2) * rsq64(l2);
+        gx += s * dx; gy += s * dy; gz += s * dz;
+        unsafeAtomicAdd(g + 4 * j + 0, -s * dx);
+        unsafeAtomicAdd(g + 4 * j + 1, -s * dy);
+        unsafeAtomicAdd(g + 4 * j + 2, -s * dz);
+    }
+    unsafeAtomicAdd(g + 4 * r + 0, gx);
+    unsafeAtomicAdd(g + 4 * r + 1, gy);
+    unsafeAtomicAdd(g + 4 * r + 2, gz);
+}
+
+// Damped velocity update and partial norms from the scattered forces.
+__global__ void __launch_bounds__(kLoopBlock) k_loop_accel(SolveArgs A, int slot, const double *g,
+                                                           double *partial)
+{
+    __shared__ double red[(kLoopBlock / kWave) * kRedStride];
+    const int p = A.ids ? A.ids[slot] : slot;
+    const ProbDesc P = A.probs[p];
+    double *W = A.wbuf + 4 * P.node_base;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int r = blockIdx.x * kLoopBlock + tid;
+    const double hdt = 0.5 * P.dt;
+    double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
+    if (r < P.N) {
+        const double gr[3] = {g[4 * r], g[4 * r + 1], g[4 * r + 2]};
+        const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        if (r < P.N_free) {
+            const double im = A.invm[P.node_base + r];
+            double vv = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double wa = W[4 * r + a];
+                const double acc = gr[a] * im - P.c * wa;
+                const double v = wa + hdt * acc;
+                vv += v * v;
+                W[4 * r + a] = v + hdt * acc;
+            }
+            gf2 = gg;
+            ke2 = A.mass[P.node_base + r] * vv;
+        } else {
+            gb2 = gg;
+        }
+    }
+    block_sum2<kLoopBlock / kWave>(red, lane, wave, gf2, gb2);
+    ke2 = block_sum1<kLoopBlock / kWave>(red, lane, wave, ke2);
+    if (tid == 0) {
+        partial[3 * blockIdx.x + 0] = gf2;
+        partial[3 * blockIdx.x + 1] = gb2;
+        partial[3 * blockIdx.x + 2] = ke2;
+    }
+}
+
 // Sums the block partials in order; out = {gf2, gb2, ke2}.
 __global__ void __launch_bounds__(kWave) k_loop_reduce(const double *partial, int nblk, double *out)
 {
@@ -1370,11 +1461,18 @@ int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream)
 //   phase 2: displacements, scalars and stress of the finished solve
 int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, double *partial,
                         double *out_scalars, int64_t n_done, double rho, double ke, int status,
-                        void *stream)
+                        double *gbuf, void *stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int nblk = (n_nodes + kLoopBlock - 1) / kLoopBlock;
-    if (phase == 0) {
+    if (phase == 3) {
+        // one pass with the zero + atomic-scatter force kernel
+        hipLaunchKernelGGL(k_loop_update, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot);
+        hipLaunchKernelGGL(k_loop_zero, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, gbuf);
+        hipLaunchKernelGGL(k_loop_scatter, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, gbuf);
+        hipLaunchKernelGGL(k_loop_accel, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, gbuf, partial);
+        hipLaunchKernelGGL(k_loop_reduce, dim3(1), dim3(kWave), 0, st, partial, nblk, out_scalars);
+    } else if (phase == 0) {
         hipLaunchKernelGGL(k_loop_setup, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, 0);
         hipLaunchKernelGGL(k_loop_setup, dim3(nblk), dim3(kLoopBlock), 0, st, a, slot, 1);
     } else if (phase == 1) {

@@ -122,9 +122,11 @@ struct LaunchPlan {
 
 // Implemented in dr_kernels.hip.
 int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream);
+// Launch-loop comparator: phase 0 set-up, 1 one gather pass, 3 one pass with
+// the zero + atomic-scatter force kernel (gbuf: 4 doubles per node), 2 finish.
 int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, double *partial,
                         double *out_scalars, int64_t n_done, double rho, double ke, int status,
-                        void *stream);
+                        double *gbuf, void *stream);
 int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream);
 const char *kernel_error_string(int code);
 

@@ -25,7 +25,8 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 
 # Every exported symbol of include/dr.h.
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
-           "dr_stress", "dr_advance", "dr_results", "dr_sync", "dr_solve_loop", "dr_batch_info",
+           "dr_stress", "dr_advance", "dr_results", "dr_sync", "dr_solve_loop",
+           "dr_solve_loop_scatter", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
            "dr_graph_launch", "dr_batch_destroy", "dr_last_error")
 
@@ -99,6 +100,8 @@ def load():
     lib.dr_sync.restype = C.c_int
     lib.dr_solve_loop.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
     lib.dr_solve_loop.restype = C.c_int
+    lib.dr_solve_loop_scatter.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_solve_loop_scatter.restype = C.c_int
     lib.dr_batch_info.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dr_batch_info.restype = C.c_int
     lib.dr_batch_scalars.argtypes = [vp, vp, vp, vp]
@@ -210,6 +213,12 @@ def dr_solve_loop(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start
     _check(load().dr_solve_loop(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
 
 
+def dr_solve_loop_scatter(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int = DR_START_AFFINE):
+    F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_solve_loop_scatter(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
+
+
 def dr_stress(h: int, n_ids: int, total_nodes: Optional[int] = None, want_u: bool = False) -> dict:
     sig = np.zeros((n_ids, 9)); sigf = np.zeros((n_ids, 9))
     res = np.zeros(n_ids, np.int32); it = np.zeros(n_ids, np.int64)
@@ -310,11 +319,11 @@ class DRBatch:
         dr_solve(self.h, F, ids, start)
         self._n_last = F.shape[0]
 
-    def solve_loop(self, F=None, ids=None, start=DR_START_AFFINE):
+    def solve_loop(self, F=None, ids=None, start=DR_START_AFFINE, scatter=False):
         if F is None:
             F = self.batch.F if ids is None else self.batch.F[np.asarray(ids)]
         F = np.asarray(F).reshape(-1, 9)
-        dr_solve_loop(self.h, F, ids, start)
+        (dr_solve_loop_scatter if scatter else dr_solve_loop)(self.h, F, ids, start)
         self._n_last = F.shape[0]
 
     def solve_device(self, F_dev, ids=None, start=DR_START_AFFINE):
