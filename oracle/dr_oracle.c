@@ -224,7 +224,7 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
                  double tol, long max_iter, double beta, double dt_safety,
                  double *u, double *sigma, double *sigma_fib, long *iters,
                  double *rho_out, double *ke_out, double *dt_out, double *c_out,
-                 double *rho_trace, long trace_len)
+                 double *rho_trace, long trace_len, double *work_out)
 {
     if (N < 1 || M < 0 || max_iter < 1) return OR_EINVAL;
     size_t n3 = 3 * (size_t)N;
@@ -233,14 +233,15 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
     double *v = (double *)calloc(n3, sizeof(double));
     double *a = (double *)calloc(n3, sizeof(double));
     double *g = (double *)calloc(n3, sizeof(double));
-    if (!L || !m || !v || !a || !g) {
-        free(L); free(m); free(v); free(a); free(g);
+    double *g_prev = (double *)calloc(n3, sizeof(double));
+    if (!L || !m || !v || !a || !g || !g_prev) {
+        free(L); free(m); free(v); free(a); free(g); free(g_prev);
         return OR_ENOMEM;
     }
     double dt, c, s_floor;
     int rc = oracle_derived(N, X, M, fib, EA, fixed, beta, dt_safety, L, m, &dt, &c, &s_floor);
     if (rc != 0) {
-        free(L); free(m); free(v); free(a); free(g);
+        free(L); free(m); free(v); free(a); free(g); free(g_prev);
         return rc;
     }
 
@@ -273,6 +274,12 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
 
     long n = 0;
     double t = 0.0, rho = 0.0, ke = 0.0;
+    /* Energy balance (Fig. 1, the optional check): work done by the internal
+     * forces, sum over passes of 1/2 (g_{n-1} + g_n) . du_n (trapezoid), and
+     * work dissipated by the damping force, sum of c m |v_half|^2 dt (the
+     * damping force acts with the half-step velocity, over du = dt v_half).
+     * With v = 0 at the start, KE - work_int + work_damp stays near zero. */
+    double work_int = 0.0, work_damp = 0.0;
     int status = OR_MAX_ITER;
     do {
         /* compute next time step (constant, R3) */
@@ -287,7 +294,17 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
             for (int k = 0; k < 3; ++k) u[3 * i + k] += dt * v[3 * i + k];
         }
         /* getInternalForces(u) */
+        memcpy(g_prev, g, n3 * sizeof(double));
         oracle_internal_force(N, X, u, M, fib, EA, L, g);
+        /* work of the internal and the damping forces over this step */
+        for (int i = 0; i < N; ++i) {
+            if (fixed[i]) continue;
+            for (int k = 0; k < 3; ++k) {
+                double du = dt * v[3 * i + k];
+                work_int += 0.5 * (g_prev[3 * i + k] + g[3 * i + k]) * du;
+                work_damp += c * m[i] * v[3 * i + k] * du;
+            }
+        }
         /* damping force, force residual, accelerations (free dof) */
         double gf2 = 0.0, gb2 = 0.0;
         for (int i = 0; i < N; ++i) {
@@ -333,7 +350,11 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
     *ke_out = ke;
     *dt_out = dt;
     *c_out = c;
+    if (work_out) {
+        work_out[0] = work_int;
+        work_out[1] = work_damp;
+    }
     (void)t;
-    free(L); free(m); free(v); free(a); free(g);
+    free(L); free(m); free(v); free(a); free(g); free(g_prev);
     return status;
 }

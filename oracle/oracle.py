@@ -53,7 +53,7 @@ def _load():
             C.c_double, C.c_long, C.c_double, C.c_double,
             _dp, _dp, _dp, C.POINTER(C.c_long),
             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-            C.c_void_p, C.c_long]
+            C.c_void_p, C.c_long, _dp]
         lib.oracle_internal_force.restype = None
         lib.oracle_internal_force.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip, _dp, _dp, _dp]
         lib.oracle_energy.restype = C.c_double
@@ -82,6 +82,8 @@ class OracleResult:
     dt: float
     c: float
     rho_trace: Optional[np.ndarray] = None
+    work_int: float = 0.0   # work of the internal forces over the solve (trapezoid per pass)
+    work_damp: float = 0.0  # work dissipated by the damping force
 
 
 def derived(net, beta: float, dt_safety: float):
@@ -137,15 +139,17 @@ def solve(net, F, *, tol=1e-8, max_iter=2_000_000, beta, dt_safety,
     u = np.zeros(3 * N); sig = np.zeros(9); sigf = np.zeros(9)
     it = C.c_long(); rho = C.c_double(); ke = C.c_double(); dt = C.c_double(); c = C.c_double()
     tr = np.zeros(max(trace_len, 1)) if trace_len > 0 else None
+    work = np.zeros(2)
     rc = lib.oracle_solve(N, X, M, fib, EA, fixed, Fa, int(start), Fp, up,
                           float(tol), int(max_iter), float(beta), float(dt_safety),
                           u, sig, sigf, C.byref(it), C.byref(rho), C.byref(ke), C.byref(dt), C.byref(c),
-                          tr.ctypes.data if tr is not None else None, int(trace_len))
+                          tr.ctypes.data if tr is not None else None, int(trace_len), work)
     if rc < 0:
         raise ValueError("oracle_solve: invalid input (%d)" % rc)
     return OracleResult(rc, u.reshape(N, 3), sig.reshape(3, 3), sigf.reshape(3, 3), it.value,
                         rho.value, ke.value, dt.value, c.value,
-                        tr[:min(it.value, trace_len)] if tr is not None else None)
+                        tr[:min(it.value, trace_len)] if tr is not None else None,
+                        float(work[0]), float(work[1]))
 
 
 def solve_batch(batch, *, threads: Optional[int] = None, **kw):

@@ -91,6 +91,7 @@ struct dr_batch {
     int32_t *d_ids = nullptr, *d_order = nullptr, *d_starts = nullptr;
     double *d_partial = nullptr, *d_scalars = nullptr;
     double *d_gscat = nullptr; // forces of the atomic-scatter comparator (allocated on first use)
+    double *d_enode = nullptr, *d_e_work = nullptr, *d_e_damp = nullptr; // energy balance
     // pinned staging
     double *h_F = nullptr;
     int32_t *h_ids = nullptr, *h_order = nullptr, *h_starts = nullptr;
@@ -133,7 +134,8 @@ void free_all(dr_batch *b)
                    b->d_slice_w, b->d_nbr, b->d_slice_off, b->d_kl, b->d_kl32, b->d_u, b->d_qbuf,
                    b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
-                   b->d_starts, b->d_partial, b->d_scalars, b->d_gscat};
+                   b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
+                   b->d_e_work, b->d_e_damp};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars};
@@ -183,6 +185,8 @@ dr_status validate_options(const dr_options *o)
     if (o->chunk != 0 && o->chunk != 1 && o->chunk != 2 && o->chunk != 4)
         return fail(DR_E_INVALID, "chunk must be 0, 1, 2 or 4 (got %d)", o->chunk);
     if (o->stall_window < 0) return fail(DR_E_INVALID, "stall_window must be >= 0");
+    if (!(o->energy_tol >= 0.0) || !std::isfinite(o->energy_tol))
+        return fail(DR_E_INVALID, "energy_tol must be finite and >= 0 (got %g)", o->energy_tol);
     return DR_OK;
 }
 
@@ -412,6 +416,11 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
             }
             off += (int64_t)width * drk::kWave;
         }
+        // the kernels address a problem's 16-byte incidence constants with
+        // 32-bit byte offsets
+        if (off * 16 > (int64_t)INT32_MAX)
+            return fail(DR_E_INVALID, "problem %d: %lld incidence entries exceed 2^27", p, (long long)off);
+        d.n_inc = off;
         slice_base += d.n_slices;
         inc_base += off;
         node_base += N;
@@ -479,6 +488,9 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_starts, P)
     ZS(d_partial, 3 * ((size_t)pk.n_max / 256 + 2))
     ZS(d_scalars, 8)
+    ZS(d_e_work, P)
+    ZS(d_e_damp, P)
+    if (b->opt.energy_tol > 0.0) ZS(d_enode, 4 * nodes)
 #undef ZS
     const int rc = drk::launch_fill_i32(b->d_status, DR_IDLE, (int64_t)P, st);
     if (rc != 0) return fail(DR_E_DEVICE, "status fill failed: %s", drk::kernel_error_string(rc));
@@ -500,7 +512,8 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     pl.fp32 = opt.precision == DR_FP32;
     const int elem = pl.fp32 ? 4 : 8; // bytes per state value in LDS
     const int block = opt.block;
-    auto reg_lds = [&](int blk, int n) { return (blk / drk::kWave) * 20 * 8 + 3 * n * elem; };
+    // node records (rounded up to 8 bytes), then one 160-byte record per wave
+    auto reg_lds = [&](int blk, int n) { return (blk / drk::kWave) * 20 * 8 + (3 * n * elem + 7) / 8 * 8; };
     // register-resident variant when the state fits in LDS
     int blk = block;
     if (blk == 0) blk = n_max > 2048 ? 1024 : (n_max > 256 ? 512 : 256);
@@ -685,6 +698,10 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.rho = b->d_rho;
     a.ke = b->d_ke;
     a.status = b->d_status;
+    a.energy_tol = b->opt.energy_tol;
+    a.enode = b->d_enode;
+    a.e_work = b->d_e_work;
+    a.e_damp = b->d_e_damp;
     return a;
 }
 
@@ -840,6 +857,7 @@ void dr_options_default(dr_options *o)
     o->placement = DR_PLACE_AUTO;
     o->chunk = 0;
     o->stall_window = 0;
+    o->energy_tol = 0.0;
 }
 
 const char *dr_last_error(void) { return g_err.c_str(); }
@@ -985,6 +1003,31 @@ dr_status dr_results(dr_batch *b, const int32_t *ids, int32_t n_ids, double *sig
         return fail(DR_E_NOMEM, "host allocation failed");
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_results");
+    }
+}
+
+dr_status dr_energy(dr_batch *b, const int32_t *ids, int32_t n_ids, double *work_int,
+                    double *work_damp)
+{
+    try {
+        g_err.clear();
+        if (!b) return fail(DR_E_INVALID, "batch is NULL");
+        if (!(b->opt.energy_tol > 0.0))
+            return fail(DR_E_STATE, "the batch was created without the energy balance (energy_tol 0)");
+        dr_status s = check_ids(b, ids, n_ids);
+        if (s != DR_OK) return s;
+        std::vector<double> w((size_t)b->P), d((size_t)b->P);
+        HIPCHECK(hipStreamSynchronize(b->stream));
+        HIPCHECK(hipMemcpy(w.data(), b->d_e_work, sizeof(double) * b->P, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(d.data(), b->d_e_damp, sizeof(double) * b->P, hipMemcpyDeviceToHost));
+        for (int32_t k = 0; k < n_ids; ++k) {
+            const int32_t p = ids ? ids[k] : k;
+            if (work_int) work_int[k] = w[p];
+            if (work_damp) work_damp[k] = d[p];
+        }
+        return DR_OK;
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_energy");
     }
 }
 

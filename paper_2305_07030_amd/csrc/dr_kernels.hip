@@ -35,7 +35,15 @@
 
 namespace drk {
 
+// No implicit contraction in this file: every multiply-add that the
+// iteration's state depends on is written as an explicit fma, so all kernels
+// and launch shapes round the per-node arithmetic identically (the compiler
+// would otherwise fuse differently in different instantiations).
+#pragma clang fp contract(off)
+
 enum { kConverged = 0, kMaxIter = 1, kNonFinite = 2 };
+// passes between two energy-balance checks
+constexpr int kEnergyEvery = 1024;
 
 // Progress of a running solve for the optional stall guard.
 struct Progress {
@@ -57,6 +65,13 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Index of the thread's wave in the workgroup, known to the compiler to be
+// uniform over the wave (scalar registers).
+__device__ __forceinline__ int wave_id(int tid)
+{
+    return __builtin_amdgcn_readfirstlane(tid / kWave);
+}
+
 // Wavefront sum in a fixed order: quad swaps and row rotations (DPP, within
 // rows of 16 lanes), then the two cross-row steps.  Deterministic; lane 0's
 // value is the one the callers use.
@@ -76,7 +91,6 @@ __device__ __forceinline__ double wave_sum(double v)
 // at its reference length carries exactly zero force.
 __device__ __forceinline__ double len2(double dx, double dy, double dz)
 {
-#pragma clang fp contract(off)
     return fma(dz, dz, fma(dy, dy, dx * dx));
 }
 
@@ -85,10 +99,36 @@ __device__ __forceinline__ double len2(double dx, double dy, double dz)
 // (no special-case handling: every l^2 reaching it is positive).
 __device__ __forceinline__ double rsq64(double x)
 {
-#pragma clang fp contract(off)
     const double y = __builtin_amdgcn_rsq(x);
     const double e = fma(-x * y, y, 1.0);
     return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// x^2 + y^2 + z^2 as fma(z, z, fma(y, y, x x)).
+template <class T> __device__ __forceinline__ T sq3(T x, T y, T z)
+{
+    return fma(z, z, fma(y, y, x * x));
+}
+
+// g += s d, one fma per component.
+template <class T>
+__device__ __forceinline__ void axpy3(T s, T dx, T dy, T dz, T &gx, T &gy, T &gz)
+{
+    gx = fma(s, dx, gx);
+    gy = fma(s, dy, gy);
+    gz = fma(s, dz, gz);
+}
+
+// One component of the damped velocity update (Fig. 1: damping force,
+// acceleration a = g / m - c w, then the two half-step updates w + dt/2 a):
+// returns the mid-pass velocity, leaves the new half-step velocity in w.
+template <class T>
+__device__ __forceinline__ T vel_step(T g, T im, T cdamp, T hdt, T &w)
+{
+    const T acc = fma(g, im, -(cdamp * w));
+    const T v = fma(hdt, acc, w);
+    w = fma(hdt, acc, v);
+    return v;
 }
 
 struct P64 {
@@ -101,13 +141,19 @@ struct P32 {
 };
 
 // Running state of one problem in LDS: 3 values per node, node after node
-// (one address per node, the components at immediate offsets).
+// (one address per node, the components at immediate offsets).  The byte
+// offset of a node is a 24-bit product (node ids stay below 2^21).
 template <class T> struct LdsQ {
     T *a;
     int n;
+    __device__ __forceinline__ const T *rec(int j) const
+    {
+        return reinterpret_cast<const T *>(reinterpret_cast<const char *>(a) +
+                                           __umul24((uint32_t)j, 3u * sizeof(T)));
+    }
     __device__ __forceinline__ void load(int j, T &x, T &y, T &z) const
     {
-        const T *q = a + 3 * j;
+        const T *q = rec(j);
         x = q[0]; y = q[1]; z = q[2];
     }
     __device__ __forceinline__ void store(int j, T x, T y, T z) const
@@ -124,9 +170,11 @@ template <class T> constexpr int kQStride = sizeof(T) == 8 ? 4 : 8;
 
 template <class T> struct GlbQ {
     T *base;
+    // a uniform base plus a 32-bit byte offset (node ids stay below 2^21)
     __device__ __forceinline__ void load(int j, T &x, T &y, T &z) const
     {
-        const T *q = base + kQStride<T> * (int64_t)j;
+        const T *q = reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                                 (uint32_t)j * (uint32_t)(kQStride<T> * sizeof(T)));
         x = q[0]; y = q[1]; z = q[2];
     }
     __device__ __forceinline__ void store(int j, T x, T y, T z) const
@@ -140,12 +188,12 @@ template <class T> struct GlbQ {
 // near convergence dt w falls below half an ulp of q and a plain FP32 add
 // would drop it, freezing the iteration short of equilibrium.
 template <class T>
-__device__ __forceinline__ void advance_q(T &q, T dtw, T &comp)
+__device__ __forceinline__ void advance_q(T &q, T dt, T w, T &comp)
 {
     if constexpr (sizeof(T) == 8) {
-        q += dtw;
+        q = fma(dt, w, q);
     } else {
-        const T y = dtw - comp;
+        const T y = dt * w - comp;
         const T t = q + y;
         comp = (t - q) - y;
         q = t;
@@ -202,14 +250,14 @@ __device__ __forceinline__ void chunk64(const SolveArgs &A, int64_t e, const Pos
         const double l2 = len2(dx[t], dy[t], dz[t]);
         double s = c[t].k * (l2 - c[t].L2) * rsq64(l2);
         s = (k0 + t < d) ? s : 0.0;
-        gx += s * dx[t]; gy += s * dy[t]; gz += s * dz[t];
+        axpy3(s, dx[t], dy[t], dz[t], gx, gy, gz);
         if (STRESS) {
             const double hs = 0.5 * s;
             const double dv[3] = {dx[t], dy[t], dz[t]};
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) sf[3 * p + q] += hs * dv[p] * dv[q];
+                for (int q = 0; q < 3; ++q) sf[3 * p + q] = fma(hs * dv[p], dv[q], sf[3 * p + q]);
         }
     }
 }
@@ -246,18 +294,18 @@ __device__ __forceinline__ void chunk32(const SolveArgs &A, const Aff32 &af, int
 #pragma unroll
     for (int t = 0; t < C; ++t) {
         const float X0 = c[t].dx, X1 = c[t].dy, X2 = c[t].dz;
-        const float f0 = af.F[0] * X0 + af.F[1] * X1 + af.F[2] * X2;
-        const float f1 = af.F[3] * X0 + af.F[4] * X1 + af.F[5] * X2;
-        const float f2 = af.F[6] * X0 + af.F[7] * X1 + af.F[8] * X2;
-        const float eaff = af.C[0] * X0 * X0 + af.C[1] * X1 * X1 + af.C[2] * X2 * X2 +
-                           af.C[3] * X0 * X1 + af.C[4] * X0 * X2 + af.C[5] * X1 * X2;
-        const float ex = eaff + 2.0f * (f0 * dq0[t] + f1 * dq1[t] + f2 * dq2[t]) +
-                         (dq0[t] * dq0[t] + dq1[t] * dq1[t] + dq2[t] * dq2[t]);
+        const float f0 = fma(af.F[2], X2, fma(af.F[1], X1, af.F[0] * X0));
+        const float f1 = fma(af.F[5], X2, fma(af.F[4], X1, af.F[3] * X0));
+        const float f2 = fma(af.F[8], X2, fma(af.F[7], X1, af.F[6] * X0));
+        const float eaff = fma(af.C[5] * X1, X2, fma(af.C[4] * X0, X2, fma(af.C[3] * X0, X1,
+                           fma(af.C[2] * X2, X2, fma(af.C[1] * X1, X1, af.C[0] * X0 * X0)))));
+        const float fdq = fma(f2, dq2[t], fma(f1, dq1[t], f0 * dq0[t]));
+        const float ex = fma(2.0f, fdq, eaff) + sq3(dq0[t], dq1[t], dq2[t]);
         const float dx = f0 + dq0[t], dy = f1 + dq1[t], dz = f2 + dq2[t];
-        const float l2 = dx * dx + dy * dy + dz * dz;
+        const float l2 = sq3(dx, dy, dz);
         float s = c[t].k * ex * rsqrtf(l2);
         s = (k0 + t < d) ? s : 0.0f;
-        gx += s * dx; gy += s * dy; gz += s * dz;
+        axpy3(s, dx, dy, dz, gx, gy, gz);
     }
 }
 
@@ -357,19 +405,30 @@ __device__ __forceinline__ RowHdr uniform_hdr(const RowHdr *p)
                   __builtin_amdgcn_readfirstlane(h.w)};
 }
 
-// Base pointers of one problem's incidence arrays.
+// One problem's incidence arrays as buffer resources (base, size in bytes;
+// 32-bit raw data), read with a uniform (scalar) offset for the entry and a
+// per-lane offset that stays fixed: no per-lane address arithmetic in the
+// loop, and an offset past the end reads zero instead of faulting.
+constexpr int kBufWord3 = 0x00020000; // data format 32, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_of(const void *p, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufWord3);
+}
+
 template <class Prec> struct Topo {
-    const int32_t *nbr;
-    const typename KLof<Prec>::type *kl;
+    __amdgpu_buffer_rsrc_t nbr, kl;
 };
 
 template <class Prec>
 __device__ __forceinline__ Topo<Prec> topo_of(const SolveArgs &A, const ProbDesc &P)
 {
+    using KLT = typename KLof<Prec>::type;
+    static_assert(sizeof(KLT) == 16, "16-byte incidence constants");
     Topo<Prec> t;
-    t.nbr = A.nbr + P.inc_base;
-    if constexpr (Prec::kDisp) t.kl = A.kl32 + P.inc_base;
-    else t.kl = A.kl + P.inc_base;
+    t.nbr = buf_of(A.nbr + P.inc_base, P.n_inc * 4);
+    if constexpr (Prec::kDisp) t.kl = buf_of(A.kl32 + P.inc_base, P.n_inc * 16);
+    else t.kl = buf_of(A.kl + P.inc_base, P.n_inc * 16);
     return t;
 }
 
@@ -379,12 +438,14 @@ template <class Prec, int C>
 __device__ __forceinline__ void pref_load(const Topo<Prec> &tp, RowHdr h, int k0, int lane,
                                           Pref<Prec, C> &pf)
 {
+    using KLT = typename KLof<Prec>::type;
+    const int oj = lane * 4, oc = lane * 16;
 #pragma unroll
     for (int t = 0; t < C; ++t) {
         const int k = k0 + t < h.w ? k0 + t : h.w - 1;
-        const uint32_t e = h.off + (uint32_t)(k * kWave); // uniform
-        pf.j[t] = (tp.nbr + e)[lane];
-        pf.c[t] = (tp.kl + e)[lane];
+        const int e = (int)h.off + k * kWave; // uniform
+        pf.j[t] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(tp.nbr, oj, e * 4, 0);
+        pf.c[t] = __builtin_bit_cast(KLT, __builtin_amdgcn_raw_buffer_load_b128(tp.kl, oc, e * 16, 0));
     }
 }
 
@@ -402,7 +463,7 @@ __device__ __forceinline__ void force_pre(const KL (&c)[C], const double (&px)[C
         const double dx = px[t] - xi, dy = py[t] - yi, dz = pz[t] - zi;
         const double l2 = len2(dx, dy, dz);
         const double s = c[t].k * (l2 - c[t].L2) * rsq64(l2);
-        gx += s * dx; gy += s * dy; gz += s * dz;
+        axpy3(s, dx, dy, dz, gx, gy, gz);
     }
 }
 
@@ -417,17 +478,17 @@ __device__ __forceinline__ void force_pre(const KL32 (&c)[C], const float (&px)[
         if (t > 0 && t >= nv) break;
         const float dq0 = px[t] - qi0, dq1 = py[t] - qi1, dq2 = pz[t] - qi2;
         const float X0 = c[t].dx, X1 = c[t].dy, X2 = c[t].dz;
-        const float f0 = af.F[0] * X0 + af.F[1] * X1 + af.F[2] * X2;
-        const float f1 = af.F[3] * X0 + af.F[4] * X1 + af.F[5] * X2;
-        const float f2 = af.F[6] * X0 + af.F[7] * X1 + af.F[8] * X2;
-        const float eaff = af.C[0] * X0 * X0 + af.C[1] * X1 * X1 + af.C[2] * X2 * X2 +
-                           af.C[3] * X0 * X1 + af.C[4] * X0 * X2 + af.C[5] * X1 * X2;
-        const float ex = eaff + 2.0f * (f0 * dq0 + f1 * dq1 + f2 * dq2) +
-                         (dq0 * dq0 + dq1 * dq1 + dq2 * dq2);
+        const float f0 = fma(af.F[2], X2, fma(af.F[1], X1, af.F[0] * X0));
+        const float f1 = fma(af.F[5], X2, fma(af.F[4], X1, af.F[3] * X0));
+        const float f2 = fma(af.F[8], X2, fma(af.F[7], X1, af.F[6] * X0));
+        const float eaff = fma(af.C[5] * X1, X2, fma(af.C[4] * X0, X2, fma(af.C[3] * X0, X1,
+                           fma(af.C[2] * X2, X2, fma(af.C[1] * X1, X1, af.C[0] * X0 * X0)))));
+        const float fdq = fma(f2, dq2, fma(f1, dq1, f0 * dq0));
+        const float ex = fma(2.0f, fdq, eaff) + sq3(dq0, dq1, dq2);
         const float dx = f0 + dq0, dy = f1 + dq1, dz = f2 + dq2;
-        const float l2 = dx * dx + dy * dy + dz * dz;
+        const float l2 = sq3(dx, dy, dz);
         const float s = c[t].k * ex * rsqrtf(l2);
-        gx += s * dx; gy += s * dy; gz += s * dz;
+        axpy3(s, dx, dy, dz, gx, gy, gz);
     }
 }
 
@@ -572,6 +633,77 @@ __device__ __forceinline__ double block_sum1(double *red, int lane, int wave, do
     return lane0(wave_sum(t));
 }
 
+// Four block-wide sums, with a barrier first (slots 0..3 of each wave's record).
+template <int NW>
+__device__ __forceinline__ void block_sum4(double *red, int lane, int wave, double (&v)[4])
+{
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[wave * kRedStride + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double t = lane < NW ? red[lane * kRedStride + k] : 0.0;
+        v[k] = lane0(wave_sum(t));
+    }
+}
+
+// Energy balance (Fig. 1, the optional check).  Per free node and pass, with
+// w_old / w_new the half-step velocities before / after the pass's velocity
+// updates and g the pass's internal force:
+//   e[0] += g . (w_old + w_new)   (x dt/2: the trapezoid work of g over the
+//                                  displacement steps dt w_old and dt w_new)
+//   e[1] += m |w_old|^2           (x c dt: damping work over the step)
+//   e[2]  = g . w_new             (the forward half of the last pass)
+// so W = dt/2 (sum e[0] - sum e[2]) and D = c dt sum e[1] once a solve has
+// finished (while it runs, the forward half belongs to the next step).
+__device__ __forceinline__ void energy_node(const SolveArgs &A, int64_t gi, double gdot,
+                                            double mw2, double glast)
+{
+    double *e = A.enode + 4 * gi;
+    e[0] += gdot;
+    e[1] += mw2;
+    e[2] = glast;
+}
+
+// The record update of one pass, from the force g and the half-step
+// velocity w_old before the pass's velocity updates (recomputing w_new as
+// those updates do).
+template <class T>
+__device__ __forceinline__ void energy_pass(const SolveArgs &A, int64_t gi, const T (&g)[3],
+                                            const T (&wo)[3], T im, T cdamp, T hdt, double m)
+{
+    double gdot = 0.0, wo2 = 0.0, glast = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T wn = wo[a];
+        vel_step(g[a], im, cdamp, hdt, wn);
+        gdot = fma((double)g[a], (double)wo[a] + (double)wn, gdot);
+        wo2 = fma((double)wo[a], (double)wo[a], wo2);
+        glast = fma((double)g[a], (double)wn, glast);
+    }
+    energy_node(A, gi, gdot, m * wo2, glast);
+}
+
+// Work totals of a problem from the thread-summed records s = {sum e[0],
+// sum e[1], sum e[2]} (block sums).
+__device__ __forceinline__ void energy_totals(const ProbDesc &P, const double (&s)[4], bool finished,
+                                              double &W, double &D)
+{
+    W = 0.5 * P.dt * (s[0] - (finished ? s[2] : 0.0));
+    D = P.c * P.dt * s[1];
+}
+
+// The balance test of energy_tol: |KE - W + D| <= tol max(KE, |W|, D).
+__device__ __forceinline__ bool energy_ok(double tol, double KE, double W, double D)
+{
+    const double scale = fmax(KE, fmax(fabs(W), D));
+    return fabs(KE - W + D) <= tol * scale;
+}
+
 // Residual and stop test (Fig. 1: force residual, iteration count, until
 // converged), plus the optional stall guard.  rho = |g_free| / max(|g_B|,
 // s_floor) <= tol is tested in squared form, gf2 <= tol^2 max(gb2, s_floor^2),
@@ -630,6 +762,36 @@ __device__ __forceinline__ void begin_solve(const SolveArgs &A, const Slot &S)
     A.status[S.p] = kStatusRunning;
 }
 
+// Thread sums of the energy records of its free nodes (nodes s * BLOCK + t,
+// s < NPT, in the register variant; t, t + BLOCK, ... in the global one).
+template <int NPT, int BLOCK>
+__device__ __forceinline__ void energy_sum_reg(const SolveArgs &A, int64_t nb, int Nf, int t,
+                                               double (&e)[4])
+{
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+        const int r = s * BLOCK + t;
+        if (r < Nf) {
+            const double *x = A.enode + 4 * (nb + r);
+            e[0] += x[0];
+            e[1] += x[1];
+            e[2] += x[2];
+        }
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void energy_sum_glb(const SolveArgs &A, int64_t nb, int Nf, int t,
+                                               double (&e)[4])
+{
+    for (int r = t; r < Nf; r += BLOCK) {
+        const double *x = A.enode + 4 * (nb + r);
+        e[0] += x[0];
+        e[1] += x[1];
+        e[2] += x[2];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Register-resident variant
 // ---------------------------------------------------------------------------
@@ -639,15 +801,17 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     using T = typename Prec::T;
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
     // a resume of a solve that is not running is a no-op (uniform per workgroup)
     if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
     const Aff32 af = make_aff32(S.F);
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
-    double *red = smem;
-    const LdsQ<T> pos{reinterpret_cast<T *>(smem + NW * kRedStride), N};
+    // node records first (LDS address = 24-bit product), the per-wave
+    // reduction records after them
+    const LdsQ<T> pos{reinterpret_cast<T *>(smem), N};
+    double *red = smem + (3 * N * (int)sizeof(T) + 7) / 8;
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
     const int64_t nb = P.node_base;
     constexpr int QS = kQStride<T>;
@@ -702,6 +866,15 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                     const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) w[s][a] = hdt * (g[a] * im);
+                    if (A.energy_tol > 0.0) {
+                        // the record starts afresh: w_old = 0
+                        const double gw = (double)g[0] * (double)w[s][0] + (double)g[1] * (double)w[s][1] +
+                                          (double)g[2] * (double)w[s][2];
+                        double *e = A.enode + 4 * (nb + r);
+                        e[0] = gw;
+                        e[1] = 0.0;
+                        e[2] = gw;
+                    }
                 }
             }
         }
@@ -746,9 +919,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             if (r < Nf) {
                 T x, y, z;
                 pos.load(r, x, y, z);
-                advance_q(x, dt * w[s][0], cmp[s][0]);
-                advance_q(y, dt * w[s][1], cmp[s][1]);
-                advance_q(z, dt * w[s][2], cmp[s][2]);
+                advance_q(x, dt, w[s][0], cmp[s][0]);
+                advance_q(y, dt, w[s][1], cmp[s][1]);
+                advance_q(z, dt, w[s][2], cmp[s][2]);
                 pos.store(r, x, y, z);
             }
         }
@@ -788,20 +961,19 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                     force_chunk<Prec, CH>(cur, af, pos, h.w - k0, qi[0], qi[1], qi[2], g[0], g[1], g[2]);
                 }
                 if (r < N) {
-                    const double gg = (double)g[0] * (double)g[0] + (double)g[1] * (double)g[1] +
-                                      (double)g[2] * (double)g[2];
+                    const double gg = sq3((double)g[0], (double)g[1], (double)g[2]);
                     if (r < Nf) {
+                        if (A.energy_tol > 0.0)
+                            energy_pass<T>(A, nb + r, g, w[s], im, cdamp, hdt, m);
                         double vv = 0.0;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             // damping force, acceleration, partial velocity updates
-                            const T acc = g[a] * im - cdamp * w[s][a];
-                            const T v = w[s][a] + hdt * acc;
-                            vv += (double)v * (double)v;
-                            w[s][a] = v + hdt * acc;
+                            const T v = vel_step(g[a], im, cdamp, hdt, w[s][a]);
+                            vv = fma((double)v, (double)v, vv);
                         }
                         gf2 += gg;
-                        ke2 += m * vv;
+                        ke2 = fma(m, vv, ke2);
                     } else {
                         gb2 += gg;
                     }
@@ -814,11 +986,36 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         block_sum2<NW>(red, lane, wave, gf2, gb2);
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
+        if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
+            double e[4] = {0.0, 0.0, 0.0, ke2};
+            energy_sum_reg<NPT, BLOCK>(A, nb, Nf, tp, e);
+            block_sum4<NW>(red, lane, wave, e);
+            double W, D;
+            energy_totals(P, e, false, W, D);
+            if (!energy_ok(A.energy_tol, 0.5 * e[3], W, D)) {
+                status = kStatusEnergy;
+                break;
+            }
+        }
         if (n - n0 >= A.budget) break;
     }
     // kinetic energy of the last pass (reported only)
     ke2 = block_sum1<NW>(red, lane, wave, ke2);
     final_scalars(P, gf2, gb2, ke2, rho, ke);
+    if (A.energy_tol > 0.0) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0};
+        energy_sum_reg<NPT, BLOCK>(A, nb, Nf, tid, e);
+        block_sum4<NW>(red, lane, wave, e);
+        double W, D;
+        energy_totals(P, e, status != kStatusRunning, W, D);
+        if (status != kStatusRunning && status != kStatusEnergy && status != kNonFinite &&
+            !energy_ok(A.energy_tol, ke, W, D))
+            status = kStatusEnergy;
+        if (tid == 0) {
+            A.e_work[S.p] = W;
+            A.e_damp[S.p] = D;
+        }
+    }
 
     if (status != kStatusRunning) {
 #pragma unroll
@@ -875,7 +1072,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     using T = typename Prec::T;
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
     // a resume of a solve that is not running is a no-op (uniform per workgroup)
     if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
@@ -953,8 +1150,18 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             gather<Prec, 4>(A, af, node_row(A, P, r), pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
                          g[1], g[2]);
             const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
+            T wn[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) W[4 * r + a] = hdt * (g[a] * im);
+            for (int a = 0; a < 3; ++a) W[4 * r + a] = wn[a] = hdt * (g[a] * im);
+            if (A.energy_tol > 0.0) {
+                // the record starts afresh: w_old = 0
+                const double gw = (double)g[0] * (double)wn[0] + (double)g[1] * (double)wn[1] +
+                                  (double)g[2] * (double)wn[2];
+                double *e = A.enode + 4 * (nb + r);
+                e[0] = gw;
+                e[1] = 0.0;
+                e[2] = gw;
+            }
         }
     } else {
         n = A.iters[S.p];
@@ -977,7 +1184,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             if constexpr (Prec::kDisp)
                 for (int a = 0; a < 3; ++a) c[a] = Cq[QS * r + a];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) advance_q(q[a], dt * W[4 * r + a], c[a]);
+            for (int a = 0; a < 3; ++a) advance_q(q[a], dt, W[4 * r + a], c[a]);
             pos.store(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
                 for (int a = 0; a < 3; ++a) Cq[QS * r + a] = c[a];
@@ -1025,20 +1232,20 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                     // acceleration, velocity updates and norm shares
                     const int r = c0.i * BLOCK + tid;
                     if (r < N) {
-                        const double gg = (double)g[0] * (double)g[0] +
-                                          (double)g[1] * (double)g[1] +
-                                          (double)g[2] * (double)g[2];
+                        const double gg = sq3((double)g[0], (double)g[1], (double)g[2]);
                         if (r < Nf) {
+                            if (A.energy_tol > 0.0)
+                                energy_pass<T>(A, nb + r, g, n0.w, n0.im, cdamp, hdt, n0.m);
                             double vv = 0.0;
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
-                                const T acc = g[a] * n0.im - cdamp * n0.w[a];
-                                const T v = n0.w[a] + hdt * acc;
-                                vv += (double)v * (double)v;
-                                W[4 * r + a] = v + hdt * acc;
+                                T wa = n0.w[a];
+                                const T v = vel_step(g[a], n0.im, cdamp, hdt, wa);
+                                vv = fma((double)v, (double)v, vv);
+                                W[4 * r + a] = wa;
                             }
                             gf2 += gg;
-                            ke2 += n0.m * vv;
+                            ke2 = fma(n0.m, vv, ke2);
                         } else {
                             gb2 += gg;
                         }
@@ -1059,11 +1266,36 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         block_sum2<NW>(red, lane, wave, gf2, gb2);
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
+        if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
+            double e[4] = {0.0, 0.0, 0.0, ke2};
+            energy_sum_glb<BLOCK>(A, nb, Nf, tid, e);
+            block_sum4<NW>(red, lane, wave, e);
+            double W, D;
+            energy_totals(P, e, false, W, D);
+            if (!energy_ok(A.energy_tol, 0.5 * e[3], W, D)) {
+                status = kStatusEnergy;
+                break;
+            }
+        }
         if (n - n0 >= A.budget) break;
     }
     // kinetic energy of the last pass (reported only)
     ke2 = block_sum1<NW>(red, lane, wave, ke2);
     final_scalars(P, gf2, gb2, ke2, rho, ke);
+    if (A.energy_tol > 0.0) {
+        double e[4] = {0.0, 0.0, 0.0, 0.0};
+        energy_sum_glb<BLOCK>(A, nb, Nf, tid, e);
+        block_sum4<NW>(red, lane, wave, e);
+        double W, D;
+        energy_totals(P, e, status != kStatusRunning, W, D);
+        if (status != kStatusRunning && status != kStatusEnergy && status != kNonFinite &&
+            !energy_ok(A.energy_tol, ke, W, D))
+            status = kStatusEnergy;
+        if (tid == 0) {
+            A.e_work[S.p] = W;
+            A.e_damp[S.p] = D;
+        }
+    }
 
     if (status != kStatusRunning) {
         for (int r = tid; r < N; r += BLOCK) {
@@ -1098,7 +1330,7 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
 {
     __shared__ double red[(kStressBlock / kWave) * kRedStride];
     constexpr int NW = kStressBlock / kWave;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const int slot = A.order ? A.order[slot0 + (int)blockIdx.x] : slot0 + (int)blockIdx.x;
     const int p = A.ids ? A.ids[slot] : slot;
     const int st = A.status[p];
@@ -1189,9 +1421,9 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_update(SolveArgs A, int slo
     if (r < P.N_free) {
         double x, y, z;
         pos.load(r, x, y, z);
-        x += P.dt * W[4 * r + 0];
-        y += P.dt * W[4 * r + 1];
-        z += P.dt * W[4 * r + 2];
+        x = fma(P.dt, W[4 * r + 0], x);
+        y = fma(P.dt, W[4 * r + 1], y);
+        z = fma(P.dt, W[4 * r + 2], z);
         pos.store(r, x, y, z);
     }
 }
@@ -1204,7 +1436,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_force(SolveArgs A, int slot
     const ProbDesc P = A.probs[p];
     const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
     double *W = A.wbuf + 4 * P.node_base;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const int r = blockIdx.x * kLoopBlock + tid;
     const double hdt = 0.5 * P.dt;
     double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
@@ -1218,16 +1450,15 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_force(SolveArgs A, int slot
         pos.load(r, qi[0], qi[1], qi[2]);
         gather<P64, 4>(A, Aff32{}, row, pos, lane, A.deg[P.node_base + r], qi[0], qi[1], qi[2], g[0], g[1],
                        g[2]);
-        const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        const double gg = sq3(g[0], g[1], g[2]);
         if (r < P.N_free) {
             const double im = A.invm[P.node_base + r];
             double vv = 0.0;
             for (int a = 0; a < 3; ++a) {
-                const double wa = W[4 * r + a];
-                const double acc = g[a] * im - P.c * wa;
-                const double v = wa + hdt * acc;
-                vv += v * v;
-                W[4 * r + a] = v + hdt * acc;
+                double wa = W[4 * r + a];
+                const double v = vel_step(g[a], im, P.c, hdt, wa);
+                vv = fma(v, v, vv);
+                W[4 * r + a] = wa;
             }
             gf2 = gg;
             ke2 = A.mass[P.node_base + r] * vv;
@@ -1265,7 +1496,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_scatter(SolveArgs A, int sl
     const int p = A.ids ? A.ids[slot] : slot;
     const ProbDesc P = A.probs[p];
     const GlbQ<double> pos{A.qbuf + 4 * P.node_base};
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const int r = blockIdx.x * kLoopBlock + tid;
     const int wbase = blockIdx.x * kLoopBlock + wave * kWave;
     if (wbase >= P.N) return;
@@ -1285,7 +1516,7 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_scatter(SolveArgs A, int sl
         dx -= xi; dy -= yi; dz -= zi;
         const double l2 = len2(dx, dy, dz);
         const double s = c.k * (l2 - c.L2) * rsq64(l2);
-        gx += s * dx; gy += s * dy; gz += s * dz;
+        axpy3(s, dx, dy, dz, gx, gy, gz);
         unsafeAtomicAdd(g + 4 * j + 0, -s * dx);
         unsafeAtomicAdd(g + 4 * j + 1, -s * dy);
         unsafeAtomicAdd(g + 4 * j + 2, -s * dz);
@@ -1303,22 +1534,21 @@ __global__ void __launch_bounds__(kLoopBlock) k_loop_accel(SolveArgs A, int slot
     const int p = A.ids ? A.ids[slot] : slot;
     const ProbDesc P = A.probs[p];
     double *W = A.wbuf + 4 * P.node_base;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const int r = blockIdx.x * kLoopBlock + tid;
     const double hdt = 0.5 * P.dt;
     double gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     if (r < P.N) {
         const double gr[3] = {g[4 * r], g[4 * r + 1], g[4 * r + 2]};
-        const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+        const double gg = sq3(gr[0], gr[1], gr[2]);
         if (r < P.N_free) {
             const double im = A.invm[P.node_base + r];
             double vv = 0.0;
             for (int a = 0; a < 3; ++a) {
-                const double wa = W[4 * r + a];
-                const double acc = gr[a] * im - P.c * wa;
-                const double v = wa + hdt * acc;
-                vv += v * v;
-                W[4 * r + a] = v + hdt * acc;
+                double wa = W[4 * r + a];
+                const double v = vel_step(gr[a], im, P.c, hdt, wa);
+                vv = fma(v, v, vv);
+                W[4 * r + a] = wa;
             }
             gf2 = gg;
             ke2 = A.mass[P.node_base + r] * vv;

@@ -37,6 +37,7 @@ constexpr int kGlbHdrMax = 8192;
 constexpr int kStatusRunning = 3;
 constexpr int kStatusIdle = 4;
 constexpr int kStatusStalled = 5;
+constexpr int kStatusEnergy = 6;
 
 // Slot start codes: a dr_start value starts a new solve; kResume continues
 // the problem's running solve from the state saved in HBM.
@@ -53,7 +54,7 @@ struct ProbDesc {
     double dt;          // pseudo-time step
     double c;           // mass-proportional damping coefficient
     double s_floor;     // residual denominator floor
-    double pad;
+    int64_t n_inc;      // per-incidence entries of the problem (slices x 64 x width)
 };
 static_assert(sizeof(ProbDesc) == 72, "ProbDesc layout");
 
@@ -80,6 +81,7 @@ struct SolveArgs {
     int64_t max_iter;         // cap on the passes of one solve
     int64_t budget;           // cap on the passes made in this launch
     int64_t stall_window;     // 0 = off, else passes without progress that end a solve
+    double energy_tol;        // 0 = off, else the energy-balance check (enode, e_work, e_damp)
     // network (renumbered order)
     const double *X;          // [nodes * 3]
     const double *invm;       // [nodes]
@@ -109,6 +111,10 @@ struct SolveArgs {
     double *rho;              // [P]
     double *ke;               // [P]
     int32_t *status;          // [P] dr_result, kStatusRunning or kStatusIdle
+    double *enode;            // [nodes * 4] energy terms per free node (energy_tol > 0):
+                              //   sum g.(w_old + w_new), sum m |w_old|^2, last g.w_new
+    double *e_work;           // [P] work of the internal forces of the last / running solve
+    double *e_damp;           // [P] work dissipated by damping
 };
 
 // Launch shape of one batched solve.

@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 DR_OK, DR_E_INVALID, DR_E_NOMEM, DR_E_DEVICE, DR_E_STATE = 0, -1, -2, -3, -4
-DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE, DR_RUNNING, DR_IDLE, DR_STALLED = 0, 1, 2, 3, 4, 5
+DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE, DR_RUNNING, DR_IDLE, DR_STALLED, DR_ENERGY = 0, 1, 2, 3, 4, 5, 6
 DR_FP64, DR_FP32 = 0, 1
 DR_RESUME, DR_START_AFFINE, DR_START_ZERO, DR_START_WARM = -1, 0, 1, 2
 DR_PLACE_AUTO, DR_PLACE_LDS, DR_PLACE_GLOBAL = 0, 1, 2
@@ -25,7 +25,7 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 
 # Every exported symbol of include/dr.h.
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
-           "dr_stress", "dr_advance", "dr_results", "dr_sync", "dr_solve_loop",
+           "dr_stress", "dr_advance", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
            "dr_solve_loop_scatter", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
            "dr_graph_launch", "dr_batch_destroy", "dr_last_error")
@@ -56,7 +56,8 @@ class dr_options(C.Structure):
                 ("block", C.c_int32),
                 ("placement", C.c_int32),
                 ("chunk", C.c_int32),
-                ("stall_window", C.c_int64)]
+                ("stall_window", C.c_int64),
+                ("energy_tol", C.c_double)]
 
 
 _lib = None
@@ -96,6 +97,8 @@ def load():
     lib.dr_advance.restype = C.c_int
     lib.dr_results.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
     lib.dr_results.restype = C.c_int
+    lib.dr_energy.argtypes = [vp, vp, C.c_int32, vp, vp]
+    lib.dr_energy.restype = C.c_int
     lib.dr_sync.argtypes = [vp]
     lib.dr_sync.restype = C.c_int
     lib.dr_solve_loop.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
@@ -207,6 +210,13 @@ def dr_results(h: int, ids: np.ndarray) -> dict:
                 iters=it, rho=rho, ke=ke)
 
 
+def dr_energy(h: int, ids: np.ndarray) -> dict:
+    ids = np.ascontiguousarray(ids, np.int32)
+    w = np.zeros(len(ids)); d = np.zeros(len(ids))
+    _check(load().dr_energy(h, _ptr(ids), len(ids), _ptr(w), _ptr(d)))
+    return dict(work_int=w, work_damp=d)
+
+
 def dr_solve_loop(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None, start: int = DR_START_AFFINE):
     F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
     idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
@@ -302,13 +312,13 @@ class DRBatch:
 
     def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
                  block=0, placement=DR_PLACE_AUTO, chunk=0, stall_window=0, precision=DR_FP64,
-                 stream=None):
+                 energy_tol=0.0, stream=None):
         self.batch = batch
         self.P = len(batch)
         self.total_nodes = batch.total_nodes
         self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
                                 dt_safety=dt_safety, block=block, placement=placement,
-                                chunk=chunk, stall_window=stall_window)
+                                chunk=chunk, stall_window=stall_window, energy_tol=energy_tol)
         self.h = dr_batch_create(batch.packed(), self.opt, stream if stream is not None else current_stream())
         self._n_last = None
 
@@ -339,6 +349,10 @@ class DRBatch:
 
     def query(self, ids) -> dict:
         return dr_results(self.h, ids)
+
+    def energy(self, ids=None) -> dict:
+        ids = np.arange(self.P, dtype=np.int32) if ids is None else ids
+        return dr_energy(self.h, ids)
 
     def results(self, want_u=False) -> dict:
         if self._n_last is None:

@@ -42,7 +42,8 @@ def test_exports_every_declared_function(lib):
 def test_options_default(lib):
     o = dr.dr_options_default()
     assert (o.precision, o.tol, o.max_iter, o.damping, o.dt_safety, o.block, o.placement, o.chunk,
-            o.stall_window) == (dr.DR_FP64, 1e-8, 2000000, 1e-3, 0.9, 0, dr.DR_PLACE_AUTO, 0, 0)
+            o.stall_window, o.energy_tol) == (dr.DR_FP64, 1e-8, 2000000, 1e-3, 0.9, 0, dr.DR_PLACE_AUTO,
+                                              0, 0, 0.0)
 
 
 def _packed():
@@ -92,6 +93,7 @@ def test_rejects_bad_options(lib):
                               ("damping", -1.0, "damping"), ("dt_safety", 1.5, "dt_safety"),
                               ("block", 128, "block"), ("placement", 7, "placement"),
                               ("chunk", 3, "chunk"), ("stall_window", -1, "stall_window"),
+                              ("energy_tol", -0.5, "energy_tol"), ("energy_tol", float("nan"), "energy_tol"),
                               ("precision", 5, "precision")]:
         o = dr.dr_options_default()
         setattr(o, field, value)

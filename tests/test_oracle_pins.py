@@ -397,3 +397,24 @@ def test_invalid_and_nonconverged(oracle_lib):
     # an unstable time step (dt_safety far above the bound) ends NONFINITE
     r = O.solve(net, np.diag([1.02, 1, 1]), tol=1e-8, max_iter=100000, beta=0.0, dt_safety=40.0)
     assert r.status == O.NONFINITE
+
+
+def test_energy_balance_terms(oracle_lib):
+    """Fig. 1's optional energy check.  The trapezoid work of the internal
+    forces equals minus the change of the stored energy W = sum EA L
+    (lambda^3 - 3 lambda + 2) / 6 (an independent closed form) to the
+    scheme's accuracy, and KE - W_int + W_damp stays a small fraction of the
+    largest term (a few percent in the first passes, ~1e-3 at convergence)."""
+    O = oracle_lib
+    b = I.small_batch(2, 100, 300, 0.02, seed=5)
+    for i in range(len(b)):
+        net, F = b.nets[i], b.F[i]
+        E0 = O.energy(net, net.X @ (F - np.eye(3)).T)
+        for K, bal_tol in ((50, 0.06), (2000, 3e-3), (None, 3e-3)):
+            r = O.solve(net, F, tol=1e-8 if K is None else 1e-30, max_iter=K or 2_000_000, beta=1e-3,
+                        dt_safety=0.9)
+            dE = O.energy(net, r.u) - E0
+            assert abs(r.work_int + dE) <= 2e-3 * abs(dE), (K, r.work_int, dE)
+            bal = r.ke - r.work_int + r.work_damp
+            assert abs(bal) <= bal_tol * max(r.ke, abs(r.work_int), r.work_damp), (K, bal)
+            assert r.work_damp > 0.0
