@@ -72,17 +72,38 @@ __device__ __forceinline__ int wave_id(int tid)
     return __builtin_amdgcn_readfirstlane(tid / kWave);
 }
 
+// v + (v of lane ^ 16), resp. ^ 32, in every lane, with the gfx950 row
+// swaps: swapping the odd 16-lane rows of one copy of v with the even rows of
+// another leaves (row 0, row 0, row 2, row 2) and (row 1, row 1, row 3,
+// row 3), whose sum is the butterfly step; the 32-lane swap does the same
+// with the two halves.
+__device__ __forceinline__ double add_xor16(double v)
+{
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
+__device__ __forceinline__ double add_xor32(double v)
+{
+    const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
 // Wavefront sum in a fixed order: quad swaps and row rotations (DPP, within
-// rows of 16 lanes), then the two cross-row steps.  Deterministic; lane 0's
-// value is the one the callers use.
+// rows of 16 lanes), then the two cross-row steps (row swaps).
+// Deterministic; lane 0's value is the one the callers use.
 __device__ __forceinline__ double wave_sum(double v)
 {
     v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
     v += dpp_f64<0x124>(v); // row_ror:4
     v += dpp_f64<0x128>(v); // row_ror:8
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
+    v = add_xor16(v);
+    v = add_xor32(v);
     return v;
 }
 
@@ -621,6 +642,34 @@ __device__ __forceinline__ void block_sum2(double *red, int lane, int wave, doub
     b = lane0(wave_sum(tb));
 }
 
+// The pass loops split a two-value block sum around their own barrier:
+// wave_partials2 posts each wave's sums (lane 0), and after the barrier
+// block_totals2 reduces the NW records over lanes 0..NW-1 of every wave
+// (the same inputs in the same lanes, so the same rounding in every wave)
+// and takes lane 0's result, so all threads hold the same bits.  The caller guarantees that no thread still reads the previous
+// partials (a barrier since their last use).
+template <int NW>
+__device__ __forceinline__ void wave_partials2(double *red, int lane, int wave, double a, double b)
+{
+    a = wave_sum(a); b = wave_sum(b);
+    if (lane == 0) {
+        red[wave * kRedStride + 0] = a;
+        red[wave * kRedStride + 1] = b;
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void block_totals2(const double *red, int lane, double &a, double &b)
+{
+    double ta = 0.0, tb = 0.0;
+    if (lane < NW) {
+        ta = red[lane * kRedStride + 0];
+        tb = red[lane * kRedStride + 1];
+    }
+    a = lane0(wave_sum(ta));
+    b = lane0(wave_sum(tb));
+}
+
 // One block-wide sum, with a barrier first (callable right after block_sum2).
 template <int NW>
 __device__ __forceinline__ double block_sum1(double *red, int lane, int wave, double a)
@@ -906,16 +955,13 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
     }
-    for (;;) {
-        // An opaque copy of the thread index: everything derived from it
-        // (node ids, addresses) is recomputed each pass instead of being held
-        // in registers across the loop, which would spill at 1024 threads.
-        int tp = tid;
-        asm volatile("" : "+v"(tp));
-        // displacement update (free dof)
+    // displacement update of the free dof (the first step of a pass; it is
+    // taken at the end of the previous pass, once the stop test has passed,
+    // so that a finished solve keeps the state its residual belongs to)
+    auto advance_all = [&](int t) {
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
-            const int r = s * BLOCK + tp;
+            const int r = s * BLOCK + t;
             if (r < Nf) {
                 T x, y, z;
                 pos.load(r, x, y, z);
@@ -925,7 +971,17 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 pos.store(r, x, y, z);
             }
         }
-        __syncthreads();
+    };
+    advance_all(tid);
+    __syncthreads();
+    // Two barriers per pass: after the gather (the partial sums are posted)
+    // and after the displacement update.
+    for (;;) {
+        // An opaque copy of the thread index: everything derived from it
+        // (node ids, addresses) is recomputed each pass instead of being held
+        // in registers across the loop, which would spill at 1024 threads.
+        int tp = tid;
+        asm volatile("" : "+v"(tp));
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         Pref<Prec, CH> pf;
         {
@@ -983,7 +1039,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 pref_load<Prec, CH>(topo, hn, 0, lane, pf);
             }
         }
-        block_sum2<NW>(red, lane, wave, gf2, gb2);
+        wave_partials2<NW>(red, lane, wave, gf2, gb2);
+        __syncthreads();
+        block_totals2<NW>(red, lane, gf2, gb2);
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
@@ -998,6 +1056,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             }
         }
         if (n - n0 >= A.budget) break;
+        advance_all(tp);
+        __syncthreads();
     }
     // kinetic energy of the last pass (reported only)
     ke2 = block_sum1<NW>(red, lane, wave, ke2);
@@ -1177,7 +1237,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
     }
-    for (;;) {
+    // displacement update of the free dof, taken at the end of the previous
+    // pass once the stop test has passed (as in the register variant)
+    auto advance_all = [&]() {
         for (int r = tid; r < Nf; r += BLOCK) {
             T q[3], c[3] = {0, 0, 0};
             pos.load(r, q[0], q[1], q[2]);
@@ -1189,7 +1251,10 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             if constexpr (Prec::kDisp)
                 for (int a = 0; a < 3; ++a) Cq[QS * r + a] = c[a];
         }
-        __syncthreads();
+    };
+    advance_all();
+    __syncthreads();
+    for (;;) {
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         const Cur cfirst = first_from(0);
         if (cfirst.i < nrow) {
@@ -1263,7 +1328,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 }
             }
         }
-        block_sum2<NW>(red, lane, wave, gf2, gb2);
+        wave_partials2<NW>(red, lane, wave, gf2, gb2);
+        __syncthreads();
+        block_totals2<NW>(red, lane, gf2, gb2);
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
@@ -1278,6 +1345,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             }
         }
         if (n - n0 >= A.budget) break;
+        advance_all();
+        __syncthreads();
     }
     // kinetic energy of the last pass (reported only)
     ke2 = block_sum1<NW>(red, lane, wave, ke2);
