@@ -221,6 +221,33 @@ __device__ __forceinline__ void advance_q(T &q, T dt, T w, T &comp)
     }
 }
 
+// Element r of a per-node array of one problem: a uniform base plus a 32-bit
+// byte offset (a scalar-base load; node ids stay below 2^21).
+template <class E> __device__ __forceinline__ E node_at(const E *base, int r)
+{
+    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) +
+                                        (uint32_t)r * (uint32_t)sizeof(E));
+}
+
+// Record r of a per-node array with S elements per node, the same way.
+template <int S, class E> __device__ __forceinline__ E *node_rec(E *base, int r)
+{
+    return reinterpret_cast<E *>(reinterpret_cast<char *>(base) + (uint32_t)r * (uint32_t)(S * sizeof(E)));
+}
+
+// Inverse mass and mass of node r of the problem whose nodes start at nb.
+template <class Prec, class T = typename Prec::T>
+__device__ __forceinline__ void node_mass(const SolveArgs &A, int64_t nb, int r, T &im, double &m)
+{
+    if constexpr (Prec::kDisp) {
+        im = node_at(A.invm32 + nb, r);
+        m = (double)node_at(A.mass32 + nb, r);
+    } else {
+        im = node_at(A.invm + nb, r);
+        m = node_at(A.mass + nb, r);
+    }
+}
+
 // Slice of node r: first entry (without the lane offset) and width.
 struct Row {
     int64_t e0;
@@ -1000,10 +1027,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 if (r < N) pos.load(r, qi[0], qi[1], qi[2]);
                 T im = 0;
                 double m = 0.0;
-                if (r < Nf) {
-                    im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
-                    m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
-                }
+                if (r < Nf) node_mass<Prec>(A, nb, r, im, m);
                 T g[3] = {0, 0, 0};
                 for (int k0 = 0; k0 < h.w; k0 += CH) {
                     const Pref<Prec, CH> cur = pf;
@@ -1185,10 +1209,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         if (r < N) {
             pos.load(r, nd.q[0], nd.q[1], nd.q[2]);
             if (r < Nf) {
-                nd.im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
-                nd.m = Prec::kDisp ? (double)A.mass32[nb + r] : A.mass[nb + r];
+                node_mass<Prec>(A, nb, r, nd.im, nd.m);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) nd.w[a] = W[4 * r + a];
+                for (int a = 0; a < 3; ++a) nd.w[a] = node_rec<4>(W, r)[a];
             }
         }
     };
@@ -1244,12 +1267,12 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             T q[3], c[3] = {0, 0, 0};
             pos.load(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
-                for (int a = 0; a < 3; ++a) c[a] = Cq[QS * r + a];
+                for (int a = 0; a < 3; ++a) c[a] = node_rec<QS>(Cq, r)[a];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) advance_q(q[a], dt, W[4 * r + a], c[a]);
+            for (int a = 0; a < 3; ++a) advance_q(q[a], dt, node_rec<4>(W, r)[a], c[a]);
             pos.store(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
-                for (int a = 0; a < 3; ++a) Cq[QS * r + a] = c[a];
+                for (int a = 0; a < 3; ++a) node_rec<QS>(Cq, r)[a] = c[a];
         }
     };
     advance_all();
@@ -1307,7 +1330,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                                 T wa = n0.w[a];
                                 const T v = vel_step(g[a], n0.im, cdamp, hdt, wa);
                                 vv = fma((double)v, (double)v, vv);
-                                W[4 * r + a] = wa;
+                                node_rec<4>(W, r)[a] = wa;
                             }
                             gf2 += gg;
                             ke2 = fma(n0.m, vv, ke2);
