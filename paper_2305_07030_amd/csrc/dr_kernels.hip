@@ -94,14 +94,22 @@ __device__ __forceinline__ double add_xor32(double v)
 }
 
 // Wavefront sum in a fixed order: quad swaps and row rotations (DPP, within
-// rows of 16 lanes), then the two cross-row steps (row swaps).
-// Deterministic; lane 0's value is the one the callers use.
-__device__ __forceinline__ double wave_sum(double v)
+// rows of 16 lanes: row_sum), then the two cross-row steps (row swaps).
+// Deterministic; lane 0's value is the one the callers use.  The second
+// level of the block sums has its NW <= 16 partials in lanes 0..NW-1 and
+// zeros elsewhere, so row_sum alone gives lane 0 the same total.
+__device__ __forceinline__ double row_sum(double v)
 {
     v += dpp_f64<0xB1>(v);  // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);  // quad_perm [2,3,0,1]
     v += dpp_f64<0x124>(v); // row_ror:4
     v += dpp_f64<0x128>(v); // row_ror:8
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = row_sum(v);
     v = add_xor16(v);
     v = add_xor32(v);
     return v;
@@ -654,6 +662,7 @@ __device__ __forceinline__ double lane0(double v)
 template <int NW>
 __device__ __forceinline__ void block_sum2(double *red, int lane, int wave, double &a, double &b)
 {
+    static_assert(NW <= 16, "the partials fit one 16-lane row");
     a = wave_sum(a); b = wave_sum(b);
     if (lane == 0) {
         red[wave * kRedStride + 0] = a;
@@ -665,8 +674,8 @@ __device__ __forceinline__ void block_sum2(double *red, int lane, int wave, doub
         ta = red[lane * kRedStride + 0];
         tb = red[lane * kRedStride + 1];
     }
-    a = lane0(wave_sum(ta));
-    b = lane0(wave_sum(tb));
+    a = lane0(row_sum(ta));
+    b = lane0(row_sum(tb));
 }
 
 // The pass loops split a two-value block sum around their own barrier:
@@ -688,31 +697,34 @@ __device__ __forceinline__ void wave_partials2(double *red, int lane, int wave, 
 template <int NW>
 __device__ __forceinline__ void block_totals2(const double *red, int lane, double &a, double &b)
 {
+    static_assert(NW <= 16, "the partials fit one 16-lane row");
     double ta = 0.0, tb = 0.0;
     if (lane < NW) {
         ta = red[lane * kRedStride + 0];
         tb = red[lane * kRedStride + 1];
     }
-    a = lane0(wave_sum(ta));
-    b = lane0(wave_sum(tb));
+    a = lane0(row_sum(ta));
+    b = lane0(row_sum(tb));
 }
 
 // One block-wide sum, with a barrier first (callable right after block_sum2).
 template <int NW>
 __device__ __forceinline__ double block_sum1(double *red, int lane, int wave, double a)
 {
+    static_assert(NW <= 16, "the partials fit one 16-lane row");
     __syncthreads();
     a = wave_sum(a);
     if (lane == 0) red[wave * kRedStride + 2] = a;
     __syncthreads();
     const double t = lane < NW ? red[lane * kRedStride + 2] : 0.0;
-    return lane0(wave_sum(t));
+    return lane0(row_sum(t));
 }
 
 // Four block-wide sums, with a barrier first (slots 0..3 of each wave's record).
 template <int NW>
 __device__ __forceinline__ void block_sum4(double *red, int lane, int wave, double (&v)[4])
 {
+    static_assert(NW <= 16, "the partials fit one 16-lane row");
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
@@ -723,7 +735,7 @@ __device__ __forceinline__ void block_sum4(double *red, int lane, int wave, doub
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double t = lane < NW ? red[lane * kRedStride + k] : 0.0;
-        v[k] = lane0(wave_sum(t));
+        v[k] = lane0(row_sum(t));
     }
 }
 
@@ -794,13 +806,16 @@ __device__ __forceinline__ bool stop_test(const SolveArgs &A, const ProbDesc &P,
     if (!isfinite(gf2) || !isfinite(gb2)) { status = kNonFinite; return true; }
     if (gf2 <= tol2 * den2) { status = kConverged; return true; }
     if (n >= A.max_iter) { status = kMaxIter; return true; }
-    // progress: rho^2 below (1 - 1e-3)^2 of the best so far
-    if (gf2 < pg.best * den2 * 0.998001) {
-        pg.best = gf2 / den2;
-        pg.nbest = n;
-    } else if (A.stall_window > 0 && n - pg.nbest >= A.stall_window) {
-        status = kStatusStalled;
-        return true;
+    // progress (only with the stall guard on): rho^2 below (1 - 1e-3)^2 of
+    // the best so far
+    if (A.stall_window > 0) {
+        if (gf2 < pg.best * den2 * 0.998001) {
+            pg.best = gf2 / den2;
+            pg.nbest = n;
+        } else if (n - pg.nbest >= A.stall_window) {
+            status = kStatusStalled;
+            return true;
+        }
     }
     return false;
 }
