@@ -685,13 +685,33 @@ __device__ __forceinline__ void block_sum2(double *red, int lane, int wave, doub
 // and takes lane 0's result, so all threads hold the same bits.  The caller guarantees that no thread still reads the previous
 // partials (a barrier since their last use).
 template <int NW>
-__device__ __forceinline__ void wave_partials2(double *red, int lane, int wave, double a, double b)
+__device__ __forceinline__ void wave_partials2(double *red, int lane, int wave, double a, double b,
+                                               bool has_a, bool has_b)
 {
-    a = wave_sum(a); b = wave_sum(b);
+    // a wave without free (resp. prescribed) nodes holds exact zeros: its
+    // partial is 0 without the reduction (wave-uniform flags)
+    a = has_a ? wave_sum(a) : 0.0;
+    b = has_b ? wave_sum(b) : 0.0;
     if (lane == 0) {
         red[wave * kRedStride + 0] = a;
         red[wave * kRedStride + 1] = b;
     }
+}
+
+// Whether the nodes r = i BLOCK + wave 64 + lane (i >= 0, r < N) of a wave
+// include free ones (r < Nf) and prescribed ones (Nf <= r < N).
+__device__ __forceinline__ bool wave_has_free(int wave, int Nf)
+{
+    return wave * kWave < Nf;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ bool wave_has_prescribed(int wave, int Nf, int N)
+{
+    const int base = wave * kWave;
+    int i = Nf - base - (kWave - 1); // first i whose 64 nodes reach Nf
+    i = i <= 0 ? 0 : (i + BLOCK - 1) / BLOCK;
+    return Nf < N && i * BLOCK + base <= N - 1;
 }
 
 template <int NW>
@@ -993,6 +1013,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
     Progress pg{__builtin_huge_val(), n};
+    const bool has_free = wave_has_free(wave, Nf), has_pres = wave_has_prescribed<BLOCK>(wave, Nf, N);
     if (S.start == kResume) {
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
@@ -1078,7 +1099,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 pref_load<Prec, CH>(topo, hn, 0, lane, pf);
             }
         }
-        wave_partials2<NW>(red, lane, wave, gf2, gb2);
+        wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres);
         __syncthreads();
         block_totals2<NW>(red, lane, gf2, gb2);
         ++n;
@@ -1271,6 +1292,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
     Progress pg{__builtin_huge_val(), n};
+    const bool has_free = wave_has_free(wave, Nf), has_pres = wave_has_prescribed<BLOCK>(wave, Nf, N);
     if (S.start == kResume) {
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
@@ -1366,7 +1388,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 }
             }
         }
-        wave_partials2<NW>(red, lane, wave, gf2, gb2);
+        wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres);
         __syncthreads();
         block_totals2<NW>(red, lane, gf2, gb2);
         ++n;
