@@ -177,6 +177,34 @@ dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt,
                           void *hip_stream, dr_batch **out);
 
 /*
+ * Device bytes a batch of these networks and options needs when it is made
+ * with dr_batch_create_in (every device array of the batch, each rounded up
+ * to 256 bytes).  Validates and packs on the host like dr_batch_create and
+ * makes no HIP call (usable without a device).
+ *   bytes   receives the size (0 on failure)
+ * Errors: as dr_batch_create's validation.
+ */
+dr_status dr_batch_workspace_bytes(const dr_networks *nets, const dr_options *opt,
+                                   size_t *bytes);
+
+/*
+ * As dr_batch_create, with every device array of the batch carved from a
+ * caller-owned device buffer (for callers whose memory comes from their own
+ * allocator, e.g. a framework tensor); the library allocates no device
+ * memory for this batch, also not later.  Pinned host staging buffers,
+ * streams and events are still the library's.
+ *   device_workspace  device memory of the current device, 256-byte aligned;
+ *                     the caller owns it, must keep it alive and untouched
+ *                     until dr_batch_destroy, and frees it afterwards
+ *   workspace_bytes   its size, at least dr_batch_workspace_bytes
+ * Errors: DR_E_INVALID (as dr_batch_create; NULL, unaligned, foreign or too
+ * small workspace, the message gives the size needed), DR_E_DEVICE.
+ */
+dr_status dr_batch_create_in(const dr_networks *nets, const dr_options *opt,
+                             void *hip_stream, void *device_workspace,
+                             size_t workspace_bytes, dr_batch **out);
+
+/*
  * Enqueues one DR solve (Fig. 1 steps 4, 6, 7 and the loop, then the stress
  * average) for the problems listed in ids, asynchronously on the stream.
  *   F       [n_ids * 9] host, F of ids[k] at F + 9 k; copied before return

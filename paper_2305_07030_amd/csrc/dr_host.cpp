@@ -92,6 +92,12 @@ struct dr_batch {
     double *d_partial = nullptr, *d_scalars = nullptr;
     double *d_gscat = nullptr; // forces of the atomic-scatter comparator (allocated on first use)
     double *d_enode = nullptr, *d_e_work = nullptr, *d_e_damp = nullptr; // energy balance
+    // caller-owned device workspace (dr_batch_create_in): every device array
+    // is carved from it at 256-byte boundaries and never freed here;
+    // `counting` is the sizing pass of dr_batch_workspace_bytes (no HIP call)
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
+    bool counting = false;
     // pinned staging
     double *h_F = nullptr;
     int32_t *h_ids = nullptr, *h_order = nullptr, *h_starts = nullptr;
@@ -136,8 +142,9 @@ void free_all(dr_batch *b)
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
                    b->d_e_work, b->d_e_damp};
-    for (void *p : dev)
-        if (p) (void)hipFree(p);
+    if (!b->ws)
+        for (void *p : dev)
+            if (p) (void)hipFree(p);
     void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
@@ -428,19 +435,44 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
     return DR_OK;
 }
 
-template <class T> dr_status dev_upload(T **dst, const std::vector<T> &src, hipStream_t st)
+constexpr size_t kWsAlign = 256;
+
+// One device array of the batch: from hipMalloc, or carved from the caller's
+// workspace, or (sizing pass) only counted.
+dr_status dev_alloc(dr_batch *b, void **dst, size_t bytes)
+{
+    bytes = (bytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+    *dst = nullptr;
+    if (b->counting) {
+        b->ws_used += bytes;
+        return DR_OK;
+    }
+    if (b->ws) {
+        if (b->ws_used + bytes > b->ws_bytes)
+            return fail(DR_E_INVALID, "the workspace of %zu bytes is too small", b->ws_bytes);
+        *dst = b->ws + b->ws_used;
+        b->ws_used += bytes;
+        return DR_OK;
+    }
+    HIPCHECK(hipMalloc(dst, bytes));
+    return DR_OK;
+}
+
+template <class T> dr_status dev_upload(dr_batch *b, T **dst, const std::vector<T> &src, hipStream_t st)
 {
     const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
-    HIPCHECK(hipMalloc(reinterpret_cast<void **>(dst), bytes));
+    dr_status s = dev_alloc(b, reinterpret_cast<void **>(dst), bytes);
+    if (s != DR_OK || b->counting) return s;
     if (!src.empty())
         HIPCHECK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
     return DR_OK;
 }
 
-template <class T> dr_status dev_zeros(T **dst, size_t n, hipStream_t st)
+template <class T> dr_status dev_zeros(dr_batch *b, T **dst, size_t n, hipStream_t st)
 {
     const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-    HIPCHECK(hipMalloc(reinterpret_cast<void **>(dst), bytes));
+    dr_status s = dev_alloc(b, reinterpret_cast<void **>(dst), bytes);
+    if (s != DR_OK || b->counting) return s;
     HIPCHECK(hipMemsetAsync(*dst, 0, bytes, st));
     return DR_OK;
 }
@@ -448,10 +480,10 @@ template <class T> dr_status dev_zeros(T **dst, size_t n, hipStream_t st)
 dr_status create_device(dr_batch *b, Packed &pk)
 {
     hipStream_t st = b->stream;
-    HIPCHECK(hipGetDevice(&b->device));
+    if (!b->counting) HIPCHECK(hipGetDevice(&b->device));
     dr_status s;
 #define UP(dst, vec)                                                                              \
-    if ((s = dev_upload(&b->dst, pk.vec, st)) != DR_OK) return s;
+    if ((s = dev_upload(b, &b->dst, pk.vec, st)) != DR_OK) return s;
     UP(d_probs, desc)
     UP(d_X, X)
     UP(d_invm, invm)
@@ -467,7 +499,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
 #undef UP
     const size_t P = (size_t)b->P, nodes = (size_t)b->total_nodes;
 #define ZS(dst, n)                                                                                \
-    if ((s = dev_zeros(&b->dst, (n), st)) != DR_OK) return s;
+    if ((s = dev_zeros(b, &b->dst, (n), st)) != DR_OK) return s;
     ZS(d_u, 3 * nodes)
     ZS(d_qbuf, 4 * nodes)
     ZS(d_wbuf, 4 * nodes)
@@ -491,7 +523,11 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_e_work, P)
     ZS(d_e_damp, P)
     if (b->opt.energy_tol > 0.0) ZS(d_enode, 4 * nodes)
+    // with a caller-owned workspace the scatter comparator's force buffer is
+    // carved up front (it is allocated on first use otherwise)
+    if (b->ws || b->counting) ZS(d_gscat, 4 * (size_t)std::max(pk.n_max, 1))
 #undef ZS
+    if (b->counting) return DR_OK;
     const int rc = drk::launch_fill_i32(b->d_status, DR_IDLE, (int64_t)P, st);
     if (rc != 0) return fail(DR_E_DEVICE, "status fill failed: %s", drk::kernel_error_string(rc));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_F), 9 * P * sizeof(double), 0));
@@ -843,6 +879,79 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
 
 } // namespace
 
+namespace {
+
+// Validation, packing and device set-up shared by dr_batch_create,
+// dr_batch_create_in (device arrays carved from ws) and
+// dr_batch_workspace_bytes (counting: sizes only, no HIP call).
+dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_stream, char *ws,
+                      size_t ws_bytes, bool counting, dr_batch **out, size_t *bytes)
+{
+    dr_status s = validate_options(opt);
+    if (s != DR_OK) return s;
+    Packed pk;
+    s = pack(nets, opt, pk);
+    if (s != DR_OK) return s;
+    if (plan_for(*opt, pk.n_max).npt < 0)
+        return fail(DR_E_INVALID, "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
+                    pk.n_max, opt->block);
+    if (ws) {
+        hipPointerAttribute_t attr;
+        int dev = -1;
+        if (hipPointerGetAttributes(&attr, ws) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+            hipGetDevice(&dev) != hipSuccess || attr.device != dev) {
+            (void)hipGetLastError();
+            return fail(DR_E_INVALID, "device_workspace is not device memory of the current device");
+        }
+    }
+    dr_batch *b = new dr_batch();
+    b->opt = *opt;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->P = nets->n_problems;
+    b->total_nodes = nets->node_offsets[b->P];
+    b->total_fibers = nets->fiber_offsets[b->P];
+    b->total_slices = (int64_t)pk.slice_w.size();
+    b->total_inc = (int64_t)pk.nbr.size();
+    b->n_max = pk.n_max;
+    b->desc = pk.desc;
+    b->running.assign(b->P, 0);
+    b->hp = std::move(pk.hp);
+    if (ws || counting) {
+        // sizing pass (no HIP call), then the workspace check
+        b->counting = true;
+        s = create_device(b, pk);
+        const size_t need = b->ws_used;
+        b->counting = false;
+        b->ws_used = 0;
+        if (s == DR_OK && counting) *bytes = need;
+        if (s != DR_OK || counting) {
+            delete b;
+            return s;
+        }
+        if (need > ws_bytes) {
+            delete b;
+            return fail(DR_E_INVALID, "the workspace holds %zu bytes; the batch needs %zu", ws_bytes, need);
+        }
+        b->ws = ws;
+        b->ws_bytes = ws_bytes;
+    }
+    s = create_device(b, pk);
+    if (s == DR_OK) s = build_classes(b, {});
+    if (s == DR_OK) {
+        hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e != hipSuccess) s = fail(DR_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    if (s != DR_OK) {
+        free_all(b);
+        delete b;
+        return s;
+    }
+    *out = b;
+    return DR_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 void dr_options_default(dr_options *o)
@@ -869,44 +978,44 @@ dr_status dr_batch_create(const dr_networks *nets, const dr_options *opt, void *
         g_err.clear();
         if (!out) return fail(DR_E_INVALID, "out is NULL");
         *out = nullptr;
-        dr_status s = validate_options(opt);
-        if (s != DR_OK) return s;
-        Packed pk;
-        s = pack(nets, opt, pk);
-        if (s != DR_OK) return s;
-        if (plan_for(*opt, pk.n_max).npt < 0)
-            return fail(DR_E_INVALID,
-                        "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
-                        pk.n_max, opt->block);
-        dr_batch *b = new dr_batch();
-        b->opt = *opt;
-        b->stream = reinterpret_cast<hipStream_t>(hip_stream);
-        b->P = nets->n_problems;
-        b->total_nodes = nets->node_offsets[b->P];
-        b->total_fibers = nets->fiber_offsets[b->P];
-        b->total_slices = (int64_t)pk.slice_w.size();
-        b->total_inc = (int64_t)pk.nbr.size();
-        b->n_max = pk.n_max;
-        b->desc = pk.desc;
-        b->running.assign(b->P, 0);
-        b->hp = std::move(pk.hp);
-        s = create_device(b, pk);
-        if (s == DR_OK) s = build_classes(b, {});
-        if (s == DR_OK) {
-            hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-            if (e != hipSuccess) s = fail(DR_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
-        }
-        if (s != DR_OK) {
-            free_all(b);
-            delete b;
-            return s;
-        }
-        *out = b;
-        return DR_OK;
+        return create_impl(nets, opt, hip_stream, nullptr, 0, false, out, nullptr);
     } catch (const std::bad_alloc &) {
         return fail(DR_E_NOMEM, "host allocation failed");
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_batch_create");
+    }
+}
+
+dr_status dr_batch_workspace_bytes(const dr_networks *nets, const dr_options *opt, size_t *bytes)
+{
+    try {
+        g_err.clear();
+        if (!bytes) return fail(DR_E_INVALID, "bytes is NULL");
+        *bytes = 0;
+        return create_impl(nets, opt, nullptr, nullptr, 0, true, nullptr, bytes);
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_batch_workspace_bytes");
+    }
+}
+
+dr_status dr_batch_create_in(const dr_networks *nets, const dr_options *opt, void *hip_stream,
+                             void *device_workspace, size_t workspace_bytes, dr_batch **out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(DR_E_INVALID, "out is NULL");
+        *out = nullptr;
+        if (!device_workspace) return fail(DR_E_INVALID, "device_workspace is NULL");
+        if (reinterpret_cast<uintptr_t>(device_workspace) % kWsAlign != 0)
+            return fail(DR_E_INVALID, "device_workspace is not aligned to %zu bytes", kWsAlign);
+        return create_impl(nets, opt, hip_stream, static_cast<char *>(device_workspace), workspace_bytes,
+                           false, out, nullptr);
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_batch_create_in");
     }
 }
 

@@ -24,7 +24,8 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
                  DR_E_DEVICE: "DR_E_DEVICE", DR_E_STATE: "DR_E_STATE"}
 
 # Every exported symbol of include/dr.h.
-EXPORTS = ("dr_options_default", "dr_batch_create", "dr_solve", "dr_solve_device",
+EXPORTS = ("dr_options_default", "dr_batch_create", "dr_batch_workspace_bytes",
+           "dr_batch_create_in", "dr_solve", "dr_solve_device",
            "dr_stress", "dr_advance", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
            "dr_solve_loop_scatter", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
@@ -87,6 +88,12 @@ def load():
     lib.dr_options_default.restype = None
     lib.dr_batch_create.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options), vp, C.POINTER(vp)]
     lib.dr_batch_create.restype = C.c_int
+    lib.dr_batch_workspace_bytes.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options),
+                                             C.POINTER(C.c_size_t)]
+    lib.dr_batch_workspace_bytes.restype = C.c_int
+    lib.dr_batch_create_in.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options), vp, vp, C.c_size_t,
+                                       C.POINTER(vp)]
+    lib.dr_batch_create_in.restype = C.c_int
     lib.dr_solve.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
     lib.dr_solve.restype = C.c_int
     lib.dr_solve_device.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
@@ -175,6 +182,28 @@ def dr_batch_create(packed: dict, opt: dr_options, stream=None) -> int:
     nets, keep = pack_networks(packed)
     h = C.c_void_p()
     _check(lib.dr_batch_create(C.byref(nets), C.byref(opt), stream, C.byref(h)))
+    del keep
+    return h.value
+
+
+def dr_batch_workspace_bytes(packed: dict, opt: dr_options) -> int:
+    """Device bytes dr_batch_create_in needs (host only, no device call)."""
+    lib = load()
+    nets, keep = pack_networks(packed)
+    n = C.c_size_t()
+    _check(lib.dr_batch_workspace_bytes(C.byref(nets), C.byref(opt), C.byref(n)))
+    del keep
+    return int(n.value)
+
+
+def dr_batch_create_in(packed: dict, opt: dr_options, stream, workspace_ptr: int,
+                       workspace_bytes: int) -> int:
+    """As dr_batch_create, with the device arrays in a caller-owned buffer."""
+    lib = load()
+    nets, keep = pack_networks(packed)
+    h = C.c_void_p()
+    _check(lib.dr_batch_create_in(C.byref(nets), C.byref(opt), stream, C.c_void_p(workspace_ptr),
+                                  C.c_size_t(workspace_bytes), C.byref(h)))
     del keep
     return h.value
 
@@ -307,19 +336,35 @@ def current_stream():
     return None
 
 
+def workspace_bytes(batch, **opts) -> int:
+    """Device bytes a DRBatch of `batch` with these options needs as its
+    workspace (host only)."""
+    return dr_batch_workspace_bytes(batch.packed(), make_options(**opts))
+
+
 class DRBatch:
     """Owns one dr_batch handle for a paper_2305_07030_amd.inputs.Batch."""
 
     def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
                  block=0, placement=DR_PLACE_AUTO, chunk=0, stall_window=0, precision=DR_FP64,
-                 energy_tol=0.0, stream=None):
+                 energy_tol=0.0, stream=None, workspace=None):
+        """workspace: None (the library allocates), or a device tensor whose
+        storage holds the batch's device arrays (at least
+        workspace_bytes(...) bytes, 256-byte aligned); it is kept referenced
+        until close()."""
         self.batch = batch
         self.P = len(batch)
         self.total_nodes = batch.total_nodes
         self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
                                 dt_safety=dt_safety, block=block, placement=placement,
                                 chunk=chunk, stall_window=stall_window, energy_tol=energy_tol)
-        self.h = dr_batch_create(batch.packed(), self.opt, stream if stream is not None else current_stream())
+        st = stream if stream is not None else current_stream()
+        self.workspace = workspace
+        if workspace is None:
+            self.h = dr_batch_create(batch.packed(), self.opt, st)
+        else:
+            nbytes = workspace.numel() * workspace.element_size()
+            self.h = dr_batch_create_in(batch.packed(), self.opt, st, workspace.data_ptr(), nbytes)
         self._n_last = None
 
     def solve(self, F=None, ids=None, start=DR_START_AFFINE):
@@ -393,6 +438,7 @@ class DRBatch:
         if self.h:
             dr_batch_destroy(self.h)
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:

@@ -113,3 +113,35 @@ def test_null_arguments(lib):
     assert lib.dr_solve(None, None, None, 1, 0) == dr.DR_E_INVALID
     assert lib.dr_stress(None, None, None, None, None, None, None, None) == dr.DR_E_INVALID
     lib.dr_batch_destroy(None)  # ignored
+
+
+def test_workspace_bytes_host_only(lib):
+    import ctypes as C
+    pk = _packed()
+    nodes = int(pk["node_offsets"][-1])
+    o = dr.dr_options_default()
+    n = dr.dr_batch_workspace_bytes(pk, o)
+    # every array rounded up to 256 bytes; u (24 B) and the two 32-byte state
+    # records per node alone
+    assert n % 256 == 0 and n >= nodes * (24 + 32 + 32)
+    o2 = dr.dr_options_default(); o2.energy_tol = 0.1
+    assert dr.dr_batch_workspace_bytes(pk, o2) - n == (32 * nodes + 255) // 256 * 256  # energy records
+    o3 = dr.dr_options_default(); o3.precision = dr.DR_FP32
+    assert dr.dr_batch_workspace_bytes(pk, o3) > n  # FP32 copies of the constants
+    # the same validation as at create
+    bad = dict(pk); bad["EA"] = pk["EA"].copy(); bad["EA"][7] = np.nan
+    with pytest.raises(dr.DrError) as e:
+        dr.dr_batch_workspace_bytes(bad, o)
+    assert e.value.status == dr.DR_E_INVALID and "problem 0 fiber 7" in str(e.value)
+    # NULL and unaligned arguments are rejected before any device call
+    nets, keep = dr.pack_networks(pk)
+    sz = C.c_size_t(7)
+    assert lib.dr_batch_workspace_bytes(C.byref(nets), C.byref(o), None) == dr.DR_E_INVALID
+    assert lib.dr_batch_workspace_bytes(None, C.byref(o), C.byref(sz)) == dr.DR_E_INVALID and sz.value == 0
+    h = C.c_void_p()
+    assert lib.dr_batch_create_in(C.byref(nets), C.byref(o), None, None, 1 << 20, C.byref(h)) == dr.DR_E_INVALID
+    assert "NULL" in dr.dr_last_error() and h.value is None
+    assert lib.dr_batch_create_in(C.byref(nets), C.byref(o), None, C.c_void_p(4104), 1 << 20,
+                                  C.byref(h)) == dr.DR_E_INVALID
+    assert "aligned" in dr.dr_last_error()
+    del keep
