@@ -371,6 +371,60 @@ dr_status dr_graph_launch(dr_batch *b);
  * NULL is ignored. */
 void dr_batch_destroy(dr_batch *b);
 
+/*
+ * Serving pool (section I: the macroscale's material points request solves
+ * of their sub-problems; here a resident pool of networks served by
+ * iteration-level continuous batching over dr_advance).  A handle is used
+ * from one thread at a time.
+ *
+ * dr_pool_create: a batch of the networks (as dr_batch_create) plus an empty
+ * request queue.
+ *   state_budget_bytes  cap on the running state of in-flight solves (64 B
+ *                       per node of each), 0 = none
+ *   max_slots           cap on in-flight solves (>= 1)
+ *   tick_passes         DR passes per poll for every in-flight solve (>= 1)
+ * Errors: as dr_batch_create, DR_E_INVALID for the caps.
+ */
+typedef struct dr_pool dr_pool;
+dr_status dr_pool_create(const dr_networks *nets, const dr_options *opt, void *hip_stream,
+                         int64_t state_budget_bytes, int32_t max_slots, int64_t tick_passes,
+                         dr_pool **out);
+
+/*
+ * Queues a request: solve network id at F[9] (host, row-major; copied), warm
+ * started from the displacements its previous solve left on the device
+ * (affine if none); tag is returned with the result.  Requests of one
+ * network are served in submission order, one at a time.
+ * Errors: DR_E_INVALID (id out of range, F not finite or det F <= 0, the
+ * network alone over the state budget).
+ */
+dr_status dr_pool_submit(dr_pool *pool, int32_t id, const double *F, int64_t tag);
+
+/*
+ * One scheduling step: admits queued requests first come first served (a
+ * request whose network is in flight waits without blocking the queue; one
+ * that exceeds the slot or budget cap blocks it), runs one launch of
+ * tick_passes passes over every in-flight solve (new ones start, the others
+ * resume from their exact saved state: a result is the same bits as one
+ * dr_solve with DR_START_WARM), waits for it, and retires the finished
+ * solves.  Then returns up to max_out finished requests, oldest first (the
+ * rest stay for later polls); any output may be NULL:
+ *   tags [max_out], ids [max_out], sigma [max_out * 9], result [max_out]
+ *   (dr_result), iters [max_out]; *n_out = number returned.
+ * With nothing queued or in flight it only returns finished requests.
+ * Errors: DR_E_INVALID, DR_E_DEVICE.
+ */
+dr_status dr_pool_poll(dr_pool *pool, int32_t max_out, int64_t *tags, int32_t *ids, double *sigma,
+                       int32_t *result, int64_t *iters, int32_t *n_out);
+
+/* Counts of queued, in-flight and finished-but-unreturned requests and the
+ * running-state bytes in flight; any output may be NULL. */
+dr_status dr_pool_status(const dr_pool *pool, int32_t *queued, int32_t *in_flight,
+                         int32_t *completed, int64_t *state_bytes);
+
+/* Releases the pool and its batch (waits for its stream).  NULL is ignored. */
+void dr_pool_destroy(dr_pool *pool);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *dr_last_error(void);
 

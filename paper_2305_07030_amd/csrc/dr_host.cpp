@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -879,6 +881,50 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
 
 } // namespace
 
+
+// ---------------------------------------------------------------------------
+// Serving pool: continuous batching of solve requests over a resident batch.
+// Requests wait in a FIFO queue until admitted (a free slot, room in the
+// state budget, no other request of the same network in flight); each poll
+// is one dr_advance launch over the in-flight requests (new ones start warm
+// from the network's previous solve, the others resume) with a fixed pass
+// budget; finished solves retire into a completion queue.
+// ---------------------------------------------------------------------------
+struct dr_pool {
+    dr_batch *b = nullptr;
+    int32_t P = 0;
+    std::vector<int64_t> nodes; // per network
+    int64_t state_budget = 0;   // bytes of running state in flight; 0 = unlimited
+    int32_t max_slots = 0;
+    int64_t tick_passes = 0;
+    struct Req {
+        int32_t id;
+        int64_t tag;
+        double F[9];
+    };
+    struct Flight {
+        Req r;
+        bool started;
+    };
+    struct Done {
+        int64_t tag;
+        int32_t id;
+        int32_t result;
+        int64_t iters;
+        double sigma[9];
+    };
+    std::deque<Req> queue;
+    std::map<int32_t, Flight> active; // by network
+    int64_t bytes = 0;
+    std::deque<Done> done;
+};
+
+namespace {
+// Running state an in-flight solve keeps per node: the 32-byte state record
+// and the 32-byte velocity record.
+constexpr int64_t kPoolBytesPerNode = 64;
+} // namespace
+
 namespace {
 
 // Validation, packing and device set-up shared by dr_batch_create,
@@ -1406,6 +1452,167 @@ void dr_batch_destroy(dr_batch *b)
     (void)hipStreamSynchronize(b->stream);
     free_all(b);
     delete b;
+}
+
+dr_status dr_pool_create(const dr_networks *nets, const dr_options *opt, void *hip_stream,
+                         int64_t state_budget_bytes, int32_t max_slots, int64_t tick_passes,
+                         dr_pool **out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(DR_E_INVALID, "out is NULL");
+        *out = nullptr;
+        if (state_budget_bytes < 0)
+            return fail(DR_E_INVALID, "state_budget_bytes must be >= 0 (got %lld)", (long long)state_budget_bytes);
+        if (max_slots < 1) return fail(DR_E_INVALID, "max_slots must be >= 1 (got %d)", max_slots);
+        if (tick_passes < 1)
+            return fail(DR_E_INVALID, "tick_passes must be >= 1 (got %lld)", (long long)tick_passes);
+        dr_batch *b = nullptr;
+        dr_status s = dr_batch_create(nets, opt, hip_stream, &b);
+        if (s != DR_OK) return s;
+        dr_pool *pl = new dr_pool();
+        pl->b = b;
+        pl->P = nets->n_problems;
+        pl->nodes.resize(pl->P);
+        for (int32_t p = 0; p < pl->P; ++p) pl->nodes[p] = nets->node_offsets[p + 1] - nets->node_offsets[p];
+        pl->state_budget = state_budget_bytes;
+        pl->max_slots = max_slots;
+        pl->tick_passes = tick_passes;
+        *out = pl;
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_pool_create");
+    }
+}
+
+dr_status dr_pool_submit(dr_pool *pl, int32_t id, const double *F, int64_t tag)
+{
+    try {
+        g_err.clear();
+        if (!pl) return fail(DR_E_INVALID, "pool is NULL");
+        if (!F) return fail(DR_E_INVALID, "F is NULL");
+        if (id < 0 || id >= pl->P) return fail(DR_E_INVALID, "network %d out of range [0, %d)", id, pl->P);
+        dr_status s = check_F(F, 0);
+        if (s != DR_OK) return s;
+        const int64_t need = kPoolBytesPerNode * pl->nodes[id];
+        if (pl->state_budget > 0 && need > pl->state_budget)
+            return fail(DR_E_INVALID, "network %d alone needs %lld state bytes, over the budget of %lld", id,
+                        (long long)need, (long long)pl->state_budget);
+        dr_pool::Req r;
+        r.id = id;
+        r.tag = tag;
+        std::memcpy(r.F, F, sizeof(r.F));
+        pl->queue.push_back(r);
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_pool_submit");
+    }
+}
+
+dr_status dr_pool_poll(dr_pool *pl, int32_t max_out, int64_t *tags, int32_t *ids, double *sigma,
+                       int32_t *result, int64_t *iters, int32_t *n_out)
+{
+    try {
+        g_err.clear();
+        if (!pl) return fail(DR_E_INVALID, "pool is NULL");
+        if (!n_out) return fail(DR_E_INVALID, "n_out is NULL");
+        *n_out = 0;
+        if (max_out < 0) return fail(DR_E_INVALID, "max_out must be >= 0 (got %d)", max_out);
+        // admission, FIFO: a request whose network is busy waits without
+        // blocking the ones behind it; one blocked by slots or budget blocks
+        std::deque<dr_pool::Req> kept;
+        while (!pl->queue.empty()) {
+            const dr_pool::Req r = pl->queue.front();
+            if (pl->active.count(r.id)) {
+                kept.push_back(r);
+                pl->queue.pop_front();
+                continue;
+            }
+            const int64_t need = kPoolBytesPerNode * pl->nodes[r.id];
+            if ((int32_t)pl->active.size() >= pl->max_slots ||
+                (pl->state_budget > 0 && pl->bytes + need > pl->state_budget))
+                break;
+            pl->active[r.id] = dr_pool::Flight{r, false};
+            pl->bytes += need;
+            pl->queue.pop_front();
+        }
+        for (auto it = pl->queue.begin(); it != pl->queue.end(); ++it) kept.push_back(*it);
+        pl->queue.swap(kept);
+        // one tick over the in-flight requests
+        const int32_t n = (int32_t)pl->active.size();
+        if (n > 0) {
+            std::vector<int32_t> slot_ids(n), starts(n), res(n);
+            std::vector<double> F(9 * (size_t)n), sig(9 * (size_t)n);
+            std::vector<int64_t> it(n);
+            int32_t k = 0;
+            for (auto &kv : pl->active) {
+                slot_ids[k] = kv.first;
+                starts[k] = kv.second.started ? DR_RESUME : DR_START_WARM;
+                std::memcpy(&F[9 * (size_t)k], kv.second.r.F, 9 * sizeof(double));
+                ++k;
+            }
+            dr_status s = dr_advance(pl->b, F.data(), slot_ids.data(), starts.data(), n, pl->tick_passes);
+            if (s != DR_OK) return s;
+            for (auto &kv : pl->active) kv.second.started = true;
+            s = dr_results(pl->b, slot_ids.data(), n, sig.data(), nullptr, res.data(), it.data(), nullptr,
+                           nullptr);
+            if (s != DR_OK) return s;
+            for (k = 0; k < n; ++k) {
+                if (res[k] == DR_RUNNING) continue;
+                auto f = pl->active.find(slot_ids[k]);
+                dr_pool::Done d;
+                d.tag = f->second.r.tag;
+                d.id = slot_ids[k];
+                d.result = res[k];
+                d.iters = it[k];
+                std::memcpy(d.sigma, &sig[9 * (size_t)k], sizeof(d.sigma));
+                pl->done.push_back(d);
+                pl->bytes -= kPoolBytesPerNode * pl->nodes[slot_ids[k]];
+                pl->active.erase(f);
+            }
+        }
+        // completions, oldest first
+        int32_t m = 0;
+        while (m < max_out && !pl->done.empty()) {
+            const dr_pool::Done &d = pl->done.front();
+            if (tags) tags[m] = d.tag;
+            if (ids) ids[m] = d.id;
+            if (sigma) std::memcpy(sigma + 9 * (size_t)m, d.sigma, sizeof(d.sigma));
+            if (result) result[m] = d.result;
+            if (iters) iters[m] = d.iters;
+            pl->done.pop_front();
+            ++m;
+        }
+        *n_out = m;
+        return DR_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(DR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(DR_E_INVALID, "unexpected exception in dr_pool_poll");
+    }
+}
+
+dr_status dr_pool_status(const dr_pool *pl, int32_t *queued, int32_t *in_flight, int32_t *completed,
+                         int64_t *state_bytes)
+{
+    g_err.clear();
+    if (!pl) return fail(DR_E_INVALID, "pool is NULL");
+    if (queued) *queued = (int32_t)pl->queue.size();
+    if (in_flight) *in_flight = (int32_t)pl->active.size();
+    if (completed) *completed = (int32_t)pl->done.size();
+    if (state_bytes) *state_bytes = pl->bytes;
+    return DR_OK;
+}
+
+void dr_pool_destroy(dr_pool *pl)
+{
+    if (!pl) return;
+    dr_batch_destroy(pl->b);
+    delete pl;
 }
 
 } // extern "C"

@@ -29,7 +29,8 @@ EXPORTS = ("dr_options_default", "dr_batch_create", "dr_batch_workspace_bytes",
            "dr_stress", "dr_advance", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
            "dr_solve_loop_scatter", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
-           "dr_graph_launch", "dr_batch_destroy", "dr_last_error")
+           "dr_graph_launch", "dr_batch_destroy", "dr_pool_create", "dr_pool_submit", "dr_pool_poll",
+           "dr_pool_status", "dr_pool_destroy", "dr_last_error")
 
 
 class DrError(RuntimeError):
@@ -88,6 +89,17 @@ def load():
     lib.dr_options_default.restype = None
     lib.dr_batch_create.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options), vp, C.POINTER(vp)]
     lib.dr_batch_create.restype = C.c_int
+    lib.dr_pool_create.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options), vp, C.c_int64, C.c_int32,
+                                    C.c_int64, C.POINTER(vp)]
+    lib.dr_pool_create.restype = C.c_int
+    lib.dr_pool_submit.argtypes = [vp, C.c_int32, vp, C.c_int64]
+    lib.dr_pool_submit.restype = C.c_int
+    lib.dr_pool_poll.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.dr_pool_poll.restype = C.c_int
+    lib.dr_pool_status.argtypes = [vp, vp, vp, vp, vp]
+    lib.dr_pool_status.restype = C.c_int
+    lib.dr_pool_destroy.argtypes = [vp]
+    lib.dr_pool_destroy.restype = None
     lib.dr_batch_workspace_bytes.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options),
                                              C.POINTER(C.c_size_t)]
     lib.dr_batch_workspace_bytes.restype = C.c_int
@@ -334,6 +346,58 @@ def current_stream():
     except Exception:
         pass
     return None
+
+
+class Pool:
+    """The library's serving pool (dr_pool_*) over a resident batch: submit
+    requests (network, F, tag), poll() runs one scheduling step and returns
+    the finished ones."""
+
+    def __init__(self, batch, *, state_budget_bytes=0, max_slots=256, tick_passes=4000, stream=None,
+                 **opts):
+        lib = load()
+        nets, keep = pack_networks(batch.packed())
+        h = C.c_void_p()
+        _check(lib.dr_pool_create(C.byref(nets), C.byref(make_options(**opts)),
+                                  stream if stream is not None else current_stream(),
+                                  int(state_budget_bytes), int(max_slots), int(tick_passes), C.byref(h)))
+        del keep
+        self.h = h.value
+        self.cap = max(1, len(batch))
+
+    def submit(self, net: int, F, tag: int):
+        F = np.ascontiguousarray(F, np.float64).reshape(9)
+        _check(load().dr_pool_submit(self.h, int(net), _ptr(F), int(tag)))
+
+    def poll(self, max_out=None) -> dict:
+        m = self.cap if max_out is None else int(max_out)
+        tags = np.zeros(max(m, 1), np.int64)
+        ids = np.zeros(max(m, 1), np.int32)
+        sigma = np.zeros((max(m, 1), 3, 3))
+        res = np.zeros(max(m, 1), np.int32)
+        it = np.zeros(max(m, 1), np.int64)
+        n = C.c_int32()
+        _check(load().dr_pool_poll(self.h, m, _ptr(tags), _ptr(ids), _ptr(sigma), _ptr(res), _ptr(it),
+                                   C.byref(n)))
+        k = n.value
+        return dict(tags=tags[:k], ids=ids[:k], sigma=sigma[:k], result=res[:k], iters=it[:k])
+
+    def status(self) -> dict:
+        q, f, c = C.c_int32(), C.c_int32(), C.c_int32()
+        b = C.c_int64()
+        _check(load().dr_pool_status(self.h, C.byref(q), C.byref(f), C.byref(c), C.byref(b)))
+        return dict(queued=q.value, in_flight=f.value, completed=c.value, state_bytes=b.value)
+
+    def close(self):
+        if self.h:
+            load().dr_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_bytes(batch, **opts) -> int:

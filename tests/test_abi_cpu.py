@@ -145,3 +145,24 @@ def test_workspace_bytes_host_only(lib):
                                   C.byref(h)) == dr.DR_E_INVALID
     assert "aligned" in dr.dr_last_error()
     del keep
+
+
+def test_pool_arguments_checked_before_device(lib):
+    import ctypes as C
+    pk = _packed()
+    nets, keep = dr.pack_networks(pk)
+    o = dr.dr_options_default()
+    h = C.c_void_p()
+    assert lib.dr_pool_create(C.byref(nets), C.byref(o), None, 0, 4, 100, None) == dr.DR_E_INVALID
+    for budget, slots, tick, msg in [(-1, 4, 100, "state_budget_bytes"), (0, 0, 100, "max_slots"),
+                                     (0, 4, 0, "tick_passes")]:
+        assert lib.dr_pool_create(C.byref(nets), C.byref(o), None, budget, slots, tick,
+                                  C.byref(h)) == dr.DR_E_INVALID
+        assert msg in dr.dr_last_error() and h.value is None
+    F = np.eye(3).ravel()
+    n = C.c_int32(5)
+    assert lib.dr_pool_submit(None, 0, F.ctypes.data, 1) == dr.DR_E_INVALID
+    assert lib.dr_pool_poll(None, 4, None, None, None, None, None, C.byref(n)) == dr.DR_E_INVALID
+    assert lib.dr_pool_status(None, None, None, None, None) == dr.DR_E_INVALID
+    lib.dr_pool_destroy(None)  # ignored
+    del keep
