@@ -42,8 +42,8 @@ PEAK_HBM = 8.0e12
 # and the commands).  Valid only for the kernel source it was measured on:
 # any change to the kernels makes the figure null until it is measured again.
 MEASURED_TRAFFIC = {
-    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7188756487.7 KiB x 1.9997 + WRITE 18354.0 KiB x 1.0
-    "uniform": {"kernels": "73e7a21357a8f6c9", "bytes_per_launch": 1.4720283e13},
+    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7150903254.3 KiB x 1.9997 + WRITE 18354.0 KiB x 1.0
+    "uniform": {"kernels": "0e805e4a12ed714e", "bytes_per_launch": 1.4642772e13},
 }
 
 
@@ -200,7 +200,41 @@ def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
         d["offered_per_s"] = frac * sat
         out["rates"].append(d)
     dev.b.close()
+    out["native_pool_closed_loop"] = native_pool_closed_loop(batch, beta, budget, F0, n_closed)
     return out
+
+
+def native_pool_closed_loop(batch, beta, budget, F0, n_requests):
+    """The same closed loop (warm pool, every request queued at once, the same
+    request stream) through the library's own pool (dr_pool_*)."""
+    import numpy as np
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import serve as SV
+    pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=len(batch), tick_passes=4000,
+                   tol=1e-8, damping=beta, dt_safety=0.9)
+    for p in range(len(batch)):
+        pool.submit(p, F0[p], -1 - p)
+    while sum(pool.status()[k] for k in ("queued", "in_flight", "completed")) > 0:
+        pool.poll()
+    stream = SV.RequestStream(F0, 0.0, 0.002, seed=50)
+    t0 = time.perf_counter()
+    for _ in range(n_requests):
+        r = stream.make(t0)
+        pool.submit(r.net, r.F, r.rid)
+    lat, done, polls, conv = [], 0, 0, 0
+    while done < n_requests:
+        out = pool.poll()
+        polls += 1
+        now = time.perf_counter()
+        done += len(out["tags"])
+        conv += int((out["result"] == dr.DR_CONVERGED).sum())
+        lat += [now - t0] * len(out["tags"])
+    wall = time.perf_counter() - t0
+    pool.close()
+    lat = np.array(lat)
+    return {"completed": done, "polls": polls, "converged": conv, "throughput_per_s": done / wall,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
 
 
 def uneven_main(args):
