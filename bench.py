@@ -237,6 +237,84 @@ def native_pool_closed_loop(batch, beta, budget, F0, n_requests):
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
 
 
+def _pool_part(a):
+    from paper_2305_07030_amd import inputs as I
+    P, lo, hi = a
+    return I.config_pool(P, idx=list(range(lo, hi)))
+
+
+def pool_main(args):
+    """The serving configuration at its own size: a resident pool of
+    --pool-size networks (N log-uniform in [1000, 33000], FP64, tol 1e-8)
+    served by the library's pool (dr_pool_*) with a running-state budget
+    below capacity, so that admission binds.  Closed loop: --requests
+    requests (the arrival stream's pool ids and F walk) queued at once on a
+    cold pool (each network's first request starts from the affine field);
+    reports the solve rate and the latency from enqueue to sigma on the
+    host."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+
+    P = args.pool_size
+    t = time.perf_counter()
+    # networks generated in worker processes before this process touches the GPU
+    cuts = np.linspace(0, P, 17).astype(int)
+    with ProcessPoolExecutor(16) as ex:
+        parts = list(ex.map(_pool_part, [(P, int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]))
+    from paper_2305_07030_amd import inputs as I
+    batch = I.Batch([n for b in parts for n in b.nets], np.concatenate([b.F for b in parts]))
+    N = np.array([n.n_nodes for n in batch.nets])
+    M = np.array([n.n_fibers for n in batch.nets])
+    log(f"pool: {P} networks, {N.sum()} nodes, {M.sum()} fibers, generated in {time.perf_counter() - t:.1f}s")
+
+    import torch
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import serve as SV
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    budget = args.state_budget_mib << 20
+    t = time.perf_counter()
+    pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=256, tick_passes=4000, tol=1e-8,
+                   damping=1e-4, dt_safety=0.9)
+    log(f"pool created in {time.perf_counter() - t:.1f}s")
+    stream = SV.RequestStream(batch.F, 0.0, 0.002, seed=50)
+    reqs = [stream.make(0.0) for _ in range(args.requests)]
+    t0 = time.perf_counter()
+    for r in reqs:
+        pool.submit(r.net, r.F, r.rid)
+    lat, res, its, nets, polls = [], [], [], [], 0
+    t_last = t0
+    while len(lat) < len(reqs):
+        out = pool.poll()
+        polls += 1
+        now = time.perf_counter()
+        lat += [now - t0] * len(out["tags"])
+        res += out["result"].tolist()
+        its += out["iters"].tolist()
+        nets += out["ids"].tolist()
+        if now - t_last > 30:
+            st = pool.status()
+            log(f"t={now - t0:.0f}s: {len(lat)} done, {st['in_flight']} in flight, {st['queued']} queued, "
+                f"{st['state_bytes'] >> 20} MiB of state")
+            t_last = now
+    wall = time.perf_counter() - t0
+    pool.close()
+    lat = np.array(lat)
+    upd = float(sum(M[n] * i for n, i in zip(nets, its)))
+    line = {"metric": "solves/s (serving pool, closed loop)", "value": len(lat) / wall, "unit": "solves/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"pool of {P} kNN(k=3) networks, N log-uniform [1000, 33000], "
+                                   f"F walk sym U(+-0.002), FP64, tol 1e-8, damping 1e-4, cold pool",
+                       "requests": len(reqs), "state_budget_bytes": budget, "max_slots": 256,
+                       "tick_passes": 4000},
+            "wall_s": wall, "polls": polls, "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "fiber_updates_per_s": upd / wall,
+            "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
+            "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
+    print(json.dumps(line), flush=True)
+
+
 def uneven_main(args):
     """The 1024-network batch with node counts log-uniform in [2000, 33000]:
     launch shapes tuned per size bucket, the solve step captured in a HIP
@@ -371,7 +449,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "single", "uneven"])
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "single", "uneven", "pool"])
+    ap.add_argument("--pool-size", type=int, default=4096, help="pool workload: resident networks")
+    ap.add_argument("--requests", type=int, default=256, help="pool workload: closed-loop requests")
+    ap.add_argument("--state-budget-mib", type=int, default=64,
+                    help="pool workload: running-state budget of in-flight solves")
     ap.add_argument("--passes", type=int, default=20000,
                     help="uneven workload: passes per network per step")
     ap.add_argument("--converge", action="store_true",
@@ -394,6 +476,8 @@ def main():
 
     if args.workload == "uneven":
         return uneven_main(args)
+    if args.workload == "pool":
+        return pool_main(args)
 
     import numpy as np
     import torch
