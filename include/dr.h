@@ -34,8 +34,10 @@
  *   - Inputs are copied before the call returns; the caller keeps ownership
  *     of every array it passes and libdr never frees caller memory.
  *   - A dr_batch owns all device memory it allocates; dr_batch_destroy
- *     releases it.  A handle is used by one host thread at a time; all of its
- *     device work is ordered on the HIP stream given at creation.
+ *     releases it (a batch made by dr_batch_create_in allocates none: its
+ *     device arrays live in the caller's workspace).  A handle is used by one
+ *     host thread at a time; all of its device work is ordered on the HIP
+ *     stream given at creation.
  *   - F is a 3x3 deformation gradient, row-major, F[3 i + j] = dx_i / dX_j.
  *   - Node ids are the caller's (problem-local, 0-based) ids; u is always
  *     returned in the caller's node order.
