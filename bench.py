@@ -44,6 +44,10 @@ PEAK_HBM = 8.0e12
 MEASURED_TRAFFIC = {
     # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7150903254.3 KiB x 1.9997 + WRITE 18354.0 KiB x 1.0
     "uniform": {"kernels": "0e805e4a12ed714e", "bytes_per_launch": 1.4642772e13},
+    # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels of one 20 000-pass launch (default
+    # plans); k_dr_glb FETCH 37588041904.4 KiB x 1.9998 + WRITE 11060705593.3 KiB, k_dr_reg
+    # FETCH 1499180876.5 KiB x 1.9998 + WRITE 62626.6 KiB
+    "uneven": {"kernels": "0e805e4a12ed714e", "bytes_per_launch": 9.1366898e13},
 }
 
 
@@ -237,6 +241,20 @@ def native_pool_closed_loop(batch, beta, budget, F0, n_requests):
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
 
 
+def copy_calibration(mib):
+    """One plain copy of `mib` MiB (reads and writes it once), whose traffic
+    counters scale the DR kernels' (the same counters read for known bytes)."""
+    if not mib:
+        return
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB read, {mib} MiB written")
+    del x, y
+
+
 def _pool_part(a):
     from paper_2305_07030_amd import inputs as I
     P, lo, hi = a
@@ -340,9 +358,10 @@ def uneven_main(args):
     beta, K = 1e-4, args.passes
     wl = ("1024 kNN(k=3) fiber networks, N = round(exp U(ln 2000, ln 33000)), "
           "F = I + sym U(+-0.02), FP64")
+    copy_calibration(args.copy_mib)
     tuner = T.Tuner(passes=300, reps=1, confirm_passes=K, log=lambda m: log("tune:", m))
     t = time.perf_counter()
-    plans = tuner.tune(batch)
+    plans = [] if args.no_tune else tuner.tune(batch)
     tune_s = time.perf_counter() - t
     log(f"tuned in {tune_s:.1f}s:", [{k: p[k] for k in ("n_hi", "block", "chunk", "placement")}
                                      for p in plans])
@@ -403,8 +422,10 @@ def uneven_main(args):
                           "classes": default_classes},
         "roofline": {"bound": "hbm", "achieved": BYTES_PER_UPDATE * upd / kern_s / 1e9,
                      "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": BYTES_PER_UPDATE * upd / kern_s / PEAK_HBM, "traffic": None,
-                     "kernel": "k_dr_glb (the networks above the LDS limit carry most fibers)",
+                     "frac": BYTES_PER_UPDATE * upd / kern_s / PEAK_HBM,
+                     "traffic": traffic_for("uneven") if K == 20000 and not plans else None,
+                     "kernel": "k_dr_glb with k_dr_reg (the two size classes of one launch, run "
+                               "concurrently; the networks above the LDS limit carry most fibers)",
                      "kernel_ms": kern_s * 1e3, "bytes_per_update": BYTES_PER_UPDATE},
     }
     if args.converge:
@@ -456,6 +477,8 @@ def main():
                     help="pool workload: running-state budget of in-flight solves")
     ap.add_argument("--passes", type=int, default=20000,
                     help="uneven workload: passes per network per step")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uneven workload: skip the tuner (the library's default plans)")
     ap.add_argument("--converge", action="store_true",
                     help="uneven workload: also solve the batch to convergence")
     ap.add_argument("--converge-limit", type=float, default=900.0)
@@ -494,13 +517,7 @@ def main():
         batch, beta, tol = I.config_single(), 1e-3, 1e-8
         wl = "1 kNN(k=3) fiber network, N = 500, F = diag(1.01,1,1), FP64, tol 1e-8"
     log("workload:", wl, "networks", len(batch), "fibers", batch.total_fibers)
-    if args.copy_mib:
-        x = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        torch.mul(x, 1.0, out=y)  # reads and writes copy_mib MiB once each
-        torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_mib} MiB read, {args.copy_mib} MiB written")
-        del x, y
+    copy_calibration(args.copy_mib)
     stream = torch.cuda.current_stream()
     b = dr.DRBatch(batch, tol=tol, damping=beta, dt_safety=0.9, block=args.block,
                    placement=args.placement, stream=stream.cuda_stream)
