@@ -133,6 +133,32 @@ def test_fixed_pass_count_parity(block, placement):
         assert g["ke"][i] == pytest.approx(o.ke, rel=1e-6)
 
 
+def test_largest_problems_fixed_pass_count():
+    """The largest problems: 33 000 nodes (the top of the uneven workload's
+    range) and 524 288 nodes (the most one problem may have: its 8192 slice
+    headers fill the global kernel's LDS table), in global placement with
+    1024 and 512 threads, at a fixed pass count against the oracle, node by
+    node (same bar as above)."""
+    rng = np.random.default_rng(73)
+    nets = [I.draw_network(rng, 33000), I.draw_network(rng, 524288)]
+    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
+    K = 40
+    say("largest problems, N =", [n.n_nodes for n in nets], f"{K} passes")
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        ref = list(ex.map(lambda i: oracle_sensitivity(batch.nets[i], batch.F[i], K, 1e-3), range(2)))
+    for block, chunk in ((1024, 1), (512, 2)):
+        b, g = gpu_solve(batch, tol=1e-30, max_iter=K, damping=1e-3, block=block, chunk=chunk,
+                         placement=dr.DR_PLACE_GLOBAL, want_u=True)
+        b.close()
+        for i, (o, su, ss) in enumerate(ref):
+            err = np.abs(g["u_list"][i] - o.u).max()
+            say(f"block {block} chunk {chunk} net {i}: |du| {err:.2e} (sensitivity {su:.2e}), sigma rel "
+                f"{rel(g['sigma'][i], o.sigma):.2e}")
+            assert g["result"][i] == dr.DR_MAX_ITER and g["iters"][i] == K == o.iters
+            assert err < 1e-12 + 100 * su
+            assert rel(g["sigma"][i], o.sigma) < 1e-12 + 100 * ss
+
+
 def test_small_batch_converged_parity():
     batch = I.small_batch(12, 60, 650, 0.02, seed=22)
     say("12 small networks to tol 1e-8, N =", [n.n_nodes for n in batch.nets])
