@@ -166,3 +166,11 @@ def test_pool_arguments_checked_before_device(lib):
     assert lib.dr_pool_status(None, None, None, None, None) == dr.DR_E_INVALID
     lib.dr_pool_destroy(None)  # ignored
     del keep
+
+
+def test_empty_batch_rejected(lib):
+    pk = dict(node_offsets=np.zeros(1, np.int64), fiber_offsets=np.zeros(1, np.int64), X=np.zeros((0, 3)),
+              fiber_nodes=np.zeros((0, 2), np.int32), EA=np.zeros(0), fixed=np.zeros(0, np.uint8), band=0.02)
+    with pytest.raises(dr.DrError) as e:
+        dr.dr_batch_workspace_bytes(pk, dr.dr_options_default())
+    assert e.value.status == dr.DR_E_INVALID and "n_problems" in str(e.value)
