@@ -492,8 +492,9 @@ def main():
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sub-problems are independent; see the design notes on sharding).",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the sub-problems are independent: a batch splits over GPUs by estimated cost, "
+              "with no collective).",
               file=sys.stderr)
         sys.exit(2)
 
