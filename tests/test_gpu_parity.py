@@ -159,6 +159,38 @@ def test_largest_problems_fixed_pass_count():
             assert rel(g["sigma"][i], o.sigma) < 1e-12 + 100 * ss
 
 
+def test_uneven_batch_full_size_sampled():
+    """The 1024-network batch (N log-uniform in [2000, 33000]) in the launch
+    configuration of its benchmark (the library's default split: an LDS class
+    and a global class launched concurrently), at a fixed pass count:
+    sampled networks of both classes, including the largest, node by node
+    against the oracle (same bar as above); every network made the passes or
+    diverged (the collapsing-fiber case)."""
+    batch = I.config_uneven_batch(1024)
+    K = 300
+    sizes = np.array([n.n_nodes for n in batch.nets])
+    b = dr.DRBatch(batch, tol=1e-30, max_iter=K, damping=1e-4, dt_safety=S)
+    cls = b.classes()
+    say("uneven batch classes", [(c["n_lo"], c["n_hi"], c["n_problems"], c["nodes_per_thread"]) for c in cls])
+    assert len(cls) == 2 and cls[0]["nodes_per_thread"] > 0 and cls[1]["nodes_per_thread"] == 0
+    b.solve()
+    g = b.results(want_u=True)
+    assert ((g["result"] == dr.DR_MAX_ITER) | (g["result"] == dr.DR_NONFINITE)).all()
+    small = np.nonzero(sizes <= cls[0]["n_hi"])[0]
+    large = np.nonzero(sizes > cls[0]["n_hi"])[0]
+    pick = [int(small[0]), int(small[-1]), int(large[0]), int(np.argmax(sizes))]
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        ref = list(ex.map(lambda i: oracle_sensitivity(batch.nets[i], batch.F[i], K, 1e-4), pick))
+    for i, (o, su, ss) in zip(pick, ref):
+        err = np.abs(g["u_list"][i] - o.u).max()
+        say(f"net {i} (N={sizes[i]}): |du| {err:.2e} (sensitivity {su:.2e}), sigma rel "
+            f"{rel(g['sigma'][i], o.sigma):.2e}")
+        assert g["result"][i] == dr.DR_MAX_ITER and g["iters"][i] == K == o.iters
+        assert err < 1e-12 + 100 * su
+        assert rel(g["sigma"][i], o.sigma) < 1e-12 + 100 * ss
+    b.close()
+
+
 def test_small_batch_converged_parity():
     batch = I.small_batch(12, 60, 650, 0.02, seed=22)
     say("12 small networks to tol 1e-8, N =", [n.n_nodes for n in batch.nets])
