@@ -503,7 +503,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
 #define ZS(dst, n)                                                                                \
     if ((s = dev_zeros(b, &b->dst, (n), st)) != DR_OK) return s;
     ZS(d_u, 3 * nodes)
-    ZS(d_qbuf, 4 * nodes)
+    ZS(d_qbuf, 2 * 4 * nodes) // two state buffers
     ZS(d_wbuf, 4 * nodes)
     ZS(d_F_cur, 9 * P)
     ZS(d_F_last, 9 * P)
@@ -723,6 +723,7 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.kl32 = b->d_kl32;
     a.u = b->d_u;
     a.qbuf = b->d_qbuf;
+    a.qhalf = 4 * b->total_nodes;
     a.wbuf = b->d_wbuf;
     a.F_cur = b->d_F_cur;
     a.F_last = b->d_F_last;

@@ -686,15 +686,15 @@ __device__ __forceinline__ void block_sum2(double *red, int lane, int wave, doub
 // partials (a barrier since their last use).
 template <int NW>
 __device__ __forceinline__ void wave_partials2(double *red, int lane, int wave, double a, double b,
-                                               bool has_a, bool has_b)
+                                               bool has_a, bool has_b, int slot = 0)
 {
     // a wave without free (resp. prescribed) nodes holds exact zeros: its
     // partial is 0 without the reduction (wave-uniform flags)
     a = has_a ? wave_sum(a) : 0.0;
     b = has_b ? wave_sum(b) : 0.0;
     if (lane == 0) {
-        red[wave * kRedStride + 0] = a;
-        red[wave * kRedStride + 1] = b;
+        red[wave * kRedStride + slot] = a;
+        red[wave * kRedStride + slot + 1] = b;
     }
 }
 
@@ -715,13 +715,14 @@ __device__ __forceinline__ bool wave_has_prescribed(int wave, int Nf, int N)
 }
 
 template <int NW>
-__device__ __forceinline__ void block_totals2(const double *red, int lane, double &a, double &b)
+__device__ __forceinline__ void block_totals2(const double *red, int lane, double &a, double &b,
+                                              int slot = 0)
 {
     static_assert(NW <= 16, "the partials fit one 16-lane row");
     double ta = 0.0, tb = 0.0;
     if (lane < NW) {
-        ta = red[lane * kRedStride + 0];
-        tb = red[lane * kRedStride + 1];
+        ta = red[lane * kRedStride + slot];
+        tb = red[lane * kRedStride + slot + 1];
     }
     a = lane0(row_sum(ta));
     b = lane0(row_sum(tb));
@@ -926,7 +927,10 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
     const int64_t nb = P.node_base;
     constexpr int QS = kQStride<T>;
-    T *qsave = reinterpret_cast<T *>(A.qbuf) + QS * nb;
+    // the saved state after pass k lives in buffer k & 1 of the two state
+    // buffers the global variant alternates (same layout)
+    T *const qbase = reinterpret_cast<T *>(A.qbuf) + QS * nb;
+    const int64_t qhalf = A.qhalf * (int64_t)(sizeof(double) / sizeof(T));
     T *wsave = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
 
     // headers of this wave's NPT slices, read each pass from LDS
@@ -991,6 +995,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         }
     } else {
         n = A.iters[S.p];
+        const T *const qsave = qbase + (n & 1) * qhalf;
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
             const int r = s * BLOCK + tid;
@@ -1149,6 +1154,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
         }
     } else {
         // budget spent: save the exact state for the next launch
+        T *const qsave = qbase + (n & 1) * qhalf;
 #pragma unroll
         for (int s = 0; s < NPT; ++s) {
             const int r = s * BLOCK + tid;
@@ -1181,6 +1187,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 // A node's data for the force phase.
 template <class T> struct NodeData {
     T q[3];
+    T c[3]; // compensation terms of the FP32 state (zero in FP64)
     T w[3];
     T im;
     double m;
@@ -1202,8 +1209,15 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     double *red = smem;
     const int64_t nb = P.node_base;
     constexpr int QS = kQStride<T>;
-    const GlbQ<T> pos{reinterpret_cast<T *>(A.qbuf) + QS * nb};
-    T *Cq = reinterpret_cast<T *>(A.qbuf) + QS * nb + 4; // FP32 compensation terms
+    // Two state buffers: the state after pass k lives in buffer k & 1, so a
+    // pass can write each node's next state as soon as its velocity is known
+    // while the other waves still read this pass's state (no separate
+    // displacement sweep, one barrier per pass).  A record holds the FP64
+    // position, or the FP32 state and, at +4, its compensation terms.
+    T *const qbase = reinterpret_cast<T *>(A.qbuf) + QS * nb;
+    const int64_t qhalf = A.qhalf * (int64_t)(sizeof(double) / sizeof(T));
+    auto qbuf_of = [&](int64_t k) { return qbase + (k & 1) * qhalf; };
+    GlbQ<T> pos{qbase}; // the state this pass reads
     T *W = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
     using KLT = typename KLof<Prec>::type;
@@ -1239,11 +1253,16 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     auto node_data = [&](int i, NodeData<T> &nd) {
         const int r = i * BLOCK + tid;
         nd.q[0] = nd.q[1] = nd.q[2] = 0;
+        nd.c[0] = nd.c[1] = nd.c[2] = 0;
         nd.w[0] = nd.w[1] = nd.w[2] = 0;
         nd.im = 0;
         nd.m = 0.0;
         if (r < N) {
             pos.load(r, nd.q[0], nd.q[1], nd.q[2]);
+            if constexpr (Prec::kDisp)
+                if (r < Nf)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) nd.c[a] = node_rec<QS>(pos.base + 4, r)[a];
             if (r < Nf) {
                 node_mass<Prec>(A, nb, r, nd.im, nd.m);
 #pragma unroll
@@ -1257,9 +1276,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         for (int r = tid; r < N; r += BLOCK) {
             T q[3];
             start_q<Prec>(A, S, r, q);
-            pos.store(r, q[0], q[1], q[2]);
+            pos.store(r, q[0], q[1], q[2]); // buffer 0: the state after pass 0
             if constexpr (Prec::kDisp)
-                for (int a = 0; a < 3; ++a) Cq[QS * r + a] = 0;
+                for (int a = 0; a < 3; ++a) node_rec<QS>(qbase + 4, r)[a] = 0;
         }
         if (tid == 0) begin_solve(A, S);
         __syncthreads();
@@ -1297,24 +1316,35 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
     }
-    // displacement update of the free dof, taken at the end of the previous
-    // pass once the stop test has passed (as in the register variant)
-    auto advance_all = [&]() {
-        for (int r = tid; r < Nf; r += BLOCK) {
+    // The first displacement update of this launch, from the state after
+    // pass k (buffer k & 1) into buffer (k + 1) & 1; prescribed nodes are
+    // copied, so that both buffers hold them.  Later passes update their
+    // nodes' states as they finish them.
+    auto advance_from = [&](int64_t k) {
+        const GlbQ<T> src{qbuf_of(k)}, dst{qbuf_of(k + 1)};
+        for (int r = tid; r < N; r += BLOCK) {
             T q[3], c[3] = {0, 0, 0};
-            pos.load(r, q[0], q[1], q[2]);
+            src.load(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
-                for (int a = 0; a < 3; ++a) c[a] = node_rec<QS>(Cq, r)[a];
+                for (int a = 0; a < 3; ++a) c[a] = node_rec<QS>(src.base + 4, r)[a];
+            if (r < Nf)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) advance_q(q[a], dt, node_rec<4>(W, r)[a], c[a]);
-            pos.store(r, q[0], q[1], q[2]);
+                for (int a = 0; a < 3; ++a) advance_q(q[a], dt, node_rec<4>(W, r)[a], c[a]);
+            dst.store(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
-                for (int a = 0; a < 3; ++a) node_rec<QS>(Cq, r)[a] = c[a];
+                for (int a = 0; a < 3; ++a) node_rec<QS>(dst.base + 4, r)[a] = c[a];
         }
     };
-    advance_all();
+    advance_from(n);
     __syncthreads();
     for (;;) {
+        // pass n + 1 reads the state after pass n + 1's displacement update
+        // (buffer (n + 1) & 1) and writes the next one into buffer n & 1;
+        // the reduction slots alternate with the pass as well (one barrier
+        // per pass separates a pass's reads from the next pass's writes)
+        pos.base = qbuf_of(n + 1);
+        const GlbQ<T> qnext{qbuf_of(n)};
+        const int rslot = 2 * (int)(n & 1);
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         const Cur cfirst = first_from(0);
         if (cfirst.i < nrow) {
@@ -1362,13 +1392,22 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                             if (A.energy_tol > 0.0)
                                 energy_pass<T>(A, nb + r, g, n0.w, n0.im, cdamp, hdt, n0.m);
                             double vv = 0.0;
+                            T qn[3], cn[3];
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
                                 T wa = n0.w[a];
                                 const T v = vel_step(g[a], n0.im, cdamp, hdt, wa);
                                 vv = fma((double)v, (double)v, vv);
                                 node_rec<4>(W, r)[a] = wa;
+                                // the displacement update of the next pass
+                                qn[a] = n0.q[a];
+                                cn[a] = n0.c[a];
+                                advance_q(qn[a], dt, wa, cn[a]);
                             }
+                            qnext.store(r, qn[0], qn[1], qn[2]);
+                            if constexpr (Prec::kDisp)
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) node_rec<QS>(qnext.base + 4, r)[a] = cn[a];
                             gf2 += gg;
                             ke2 = fma(n0.m, vv, ke2);
                         } else {
@@ -1388,15 +1427,16 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 }
             }
         }
-        wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres);
+        wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres, rslot);
         __syncthreads();
-        block_totals2<NW>(red, lane, gf2, gb2);
+        block_totals2<NW>(red, lane, gf2, gb2, rslot);
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
             double e[4] = {0.0, 0.0, 0.0, ke2};
             energy_sum_glb<BLOCK>(A, nb, Nf, tid, e);
             block_sum4<NW>(red, lane, wave, e);
+            __syncthreads(); // its slots are read before the next pass writes any
             double W, D;
             energy_totals(P, e, false, W, D);
             if (!energy_ok(A.energy_tol, 0.5 * e[3], W, D)) {
@@ -1405,9 +1445,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             }
         }
         if (n - n0 >= A.budget) break;
-        advance_all();
-        __syncthreads();
     }
+    pos.base = qbuf_of(n); // the state after the last pass
     // kinetic energy of the last pass (reported only)
     ke2 = block_sum1<NW>(red, lane, wave, ke2);
     final_scalars(P, gf2, gb2, ke2, rho, ke);

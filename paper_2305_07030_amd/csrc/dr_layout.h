@@ -96,8 +96,11 @@ struct SolveArgs {
     const KL32 *kl32;         // [incidences] (FP32 state)
     // state kept on the device
     double *u;                // [nodes * 3] displacement of the last finished solve
-    double *qbuf;             // [nodes * 4] running state: positions (FP64) or
-                              //   displacements (FP32), 4 values per node
+    double *qbuf;             // [2 * nodes * 4] running state, two buffers of qhalf
+                              //   doubles: positions (FP64) or displacements and
+                              //   their compensation terms (FP32), 32 B per node;
+                              //   the state after pass k is in buffer k & 1
+    int64_t qhalf;            // doubles per state buffer (4 * nodes)
     double *wbuf;             // [nodes * 4] running half-step velocities
     double *F_cur;            // [P * 9] F of the current solve
     double *F_last;           // [P * 9] F of the last finished solve
