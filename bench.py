@@ -42,12 +42,12 @@ PEAK_HBM = 8.0e12
 # and the commands).  Valid only for the kernel source it was measured on:
 # any change to the kernels makes the figure null until it is measured again.
 MEASURED_TRAFFIC = {
-    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7150903254.3 KiB x 1.9997 + WRITE 18354.0 KiB x 1.0
-    "uniform": {"kernels": "0e805e4a12ed714e", "bytes_per_launch": 1.4642772e13},
+    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7148228512.9 KiB x 1.9997 + WRITE 18355.6 KiB x 1.0
+    "uniform": {"kernels": "f5dd241630f7e9e7", "bytes_per_launch": 1.4637281e13},
     # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels of one 20 000-pass launch (default
-    # plans); k_dr_glb FETCH 37588041904.4 KiB x 1.9998 + WRITE 11060705593.3 KiB, k_dr_reg
-    # FETCH 1499180876.5 KiB x 1.9998 + WRITE 62626.6 KiB
-    "uneven": {"kernels": "0e805e4a12ed714e", "bytes_per_launch": 9.1366898e13},
+    # plans); k_dr_glb FETCH 32786998365.2 KiB x 1.9997 + WRITE 11126673825.7 KiB, k_dr_reg
+    # FETCH 1499604460.5 KiB x 1.9997 + WRITE 58211.1 KiB
+    "uneven": {"kernels": "f5dd241630f7e9e7", "bytes_per_launch": 8.1601755e13},
 }
 
 
