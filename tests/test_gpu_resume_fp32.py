@@ -71,6 +71,42 @@ def test_chunked_equals_single_launch(placement):
     assert np.array_equal(u_ch, ref["u"])
 
 
+@pytest.mark.parametrize("precision", [dr.DR_FP64, dr.DR_FP32])
+def test_resume_across_placements(precision):
+    """A running solve saved by one placement resumes under the other (the
+    class plans change between launches, odd and even budgets so both state
+    buffers serve as the saved one): the same bits as one launch."""
+    batch = I.small_batch(6, 80, 500, 0.02, seed=34)
+    kw = dict(tol=1e-8 if precision == dr.DR_FP64 else 1e-6, damping=1e-3, dt_safety=S,
+              precision=precision, stall_window=50000 if precision == dr.DR_FP32 else 0)
+    one = dr.DRBatch(batch, **kw)
+    one.solve()
+    ref = one.results()
+    ch = dr.DRBatch(batch, **kw)
+    ids = np.arange(len(batch), dtype=np.int32)
+    plans = [[dict(n_hi=100000, block=512, chunk=1, placement=dr.DR_PLACE_LDS)],
+             [dict(n_hi=100000, block=1024, chunk=1, placement=dr.DR_PLACE_GLOBAL)]]
+    ch.set_class_plans(plans[0])
+    ch.advance(ids, np.full(len(ids), dr.DR_START_AFFINE, np.int32), 2999, F=batch.F)
+    k = 1
+    while True:
+        q = ch.query(ids)
+        running = ids[q["result"] == dr.DR_RUNNING]
+        if len(running) == 0:
+            break
+        ch.set_class_plans(plans[k % 2])
+        ch.advance(running, np.full(len(running), dr.DR_RESUME, np.int32), 2999 + (k % 2))
+        k += 1
+        assert k < 1000
+    say(f"precision {precision}: {k} launches, passes {list(q['iters'])}")
+    assert k > 3
+    assert np.array_equal(q["iters"], ref["iters"])
+    assert np.array_equal(q["sigma"], ref["sigma"])
+    assert np.array_equal(q["result"], ref["result"])
+    one.close()
+    ch.close()
+
+
 def test_mixed_fresh_and_resumed_slots():
     """A launch may start some problems and resume others; results equal the
     same solves run alone."""
