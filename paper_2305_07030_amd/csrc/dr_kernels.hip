@@ -192,10 +192,12 @@ template <class T> struct LdsQ {
     }
 };
 
-// Running state of a node in device memory: a 32-byte record holding the
-// FP64 position (x, y, z, -), or the FP32 state (q0, q1, q2, -) followed by
-// the compensation terms of its summed updates (c0, c1, c2, -).
-template <class T> constexpr int kQStride = sizeof(T) == 8 ? 4 : 8;
+// Running state of a node in device memory: a 24-byte record holding the
+// FP64 position (x, y, z), or a 32-byte one holding the FP32 state
+// (q0, q1, q2, -) followed by the compensation terms of its summed updates
+// (c0, c1, c2, -).  (The neighbour reads of the global variant come from
+// beyond L2; a record without padding makes them fewer bytes.)
+template <class T> constexpr int kQStride = sizeof(T) == 8 ? 3 : 8;
 
 template <class T> struct GlbQ {
     T *base;

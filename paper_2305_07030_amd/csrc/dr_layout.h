@@ -97,9 +97,10 @@ struct SolveArgs {
     // state kept on the device
     double *u;                // [nodes * 3] displacement of the last finished solve
     double *qbuf;             // [2 * nodes * 4] running state, two buffers of qhalf
-                              //   doubles: positions (FP64) or displacements and
-                              //   their compensation terms (FP32), 32 B per node;
-                              //   the state after pass k is in buffer k & 1
+                              //   doubles: positions (FP64, 24 B per node) or
+                              //   displacements and their compensation terms
+                              //   (FP32, 32 B per node); the state after pass k
+                              //   is in buffer k & 1
     int64_t qhalf;            // doubles per state buffer (4 * nodes)
     double *wbuf;             // [nodes * 4] running half-step velocities
     double *F_cur;            // [P * 9] F of the current solve
