@@ -198,6 +198,9 @@ template <class T> struct LdsQ {
 // (c0, c1, c2, -).  (The neighbour reads of the global variant come from
 // beyond L2; a record without padding makes them fewer bytes.)
 template <class T> constexpr int kQStride = sizeof(T) == 8 ? 3 : 8;
+// The half-step velocity record of a node kept between launches (and in
+// device memory by the global variant): 24 bytes in FP64, 16 in FP32.
+template <class T> constexpr int kWStride = sizeof(T) == 8 ? 3 : 4;
 
 template <class T> struct GlbQ {
     T *base;
@@ -933,7 +936,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     // buffers the global variant alternates (same layout)
     T *const qbase = reinterpret_cast<T *>(A.qbuf) + QS * nb;
     const int64_t qhalf = A.qhalf * (int64_t)(sizeof(double) / sizeof(T));
-    T *wsave = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
+    constexpr int WS = kWStride<T>;
+    T *wsave = reinterpret_cast<T *>(A.wbuf) + WS * nb;
 
     // headers of this wave's NPT slices, read each pass from LDS
     static_assert(4 + NPT <= kRedStride, "row headers fit the wave's LDS record");
@@ -1007,7 +1011,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 pos.store(r, qsave[QS * r], qsave[QS * r + 1], qsave[QS * r + 2]);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    w[s][a] = wsave[4 * r + a];
+                    w[s][a] = wsave[WS * r + a];
                     if constexpr (Prec::kDisp) cmp[s][a] = qsave[QS * r + 4 + a];
                 }
             }
@@ -1166,7 +1170,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     qsave[QS * r + a] = q[a];
-                    wsave[4 * r + a] = w[s][a];
+                    wsave[WS * r + a] = w[s][a];
                     if constexpr (Prec::kDisp) qsave[QS * r + 4 + a] = cmp[s][a];
                 }
             }
@@ -1220,7 +1224,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     const int64_t qhalf = A.qhalf * (int64_t)(sizeof(double) / sizeof(T));
     auto qbuf_of = [&](int64_t k) { return qbase + (k & 1) * qhalf; };
     GlbQ<T> pos{qbase}; // the state this pass reads
-    T *W = reinterpret_cast<T *>(A.wbuf) + 4 * nb;
+    constexpr int WS = kWStride<T>;
+    T *W = reinterpret_cast<T *>(A.wbuf) + WS * nb;
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
     using KLT = typename KLof<Prec>::type;
 
@@ -1268,7 +1273,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             if (r < Nf) {
                 node_mass<Prec>(A, nb, r, nd.im, nd.m);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) nd.w[a] = node_rec<4>(W, r)[a];
+                for (int a = 0; a < 3; ++a) nd.w[a] = node_rec<WS>(W, r)[a];
             }
         }
     };
@@ -1292,7 +1297,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             const T im = Prec::kDisp ? (T)A.invm32[nb + r] : (T)A.invm[nb + r];
             T wn[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) W[4 * r + a] = wn[a] = hdt * (g[a] * im);
+            for (int a = 0; a < 3; ++a) node_rec<WS>(W, r)[a] = wn[a] = hdt * (g[a] * im);
             if (A.energy_tol > 0.0) {
                 // the record starts afresh: w_old = 0
                 const double gw = (double)g[0] * (double)wn[0] + (double)g[1] * (double)wn[1] +
@@ -1331,7 +1336,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 for (int a = 0; a < 3; ++a) c[a] = node_rec<QS>(src.base + 4, r)[a];
             if (r < Nf)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) advance_q(q[a], dt, node_rec<4>(W, r)[a], c[a]);
+                for (int a = 0; a < 3; ++a) advance_q(q[a], dt, node_rec<WS>(W, r)[a], c[a]);
             dst.store(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
                 for (int a = 0; a < 3; ++a) node_rec<QS>(dst.base + 4, r)[a] = c[a];
@@ -1400,7 +1405,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                                 T wa = n0.w[a];
                                 const T v = vel_step(g[a], n0.im, cdamp, hdt, wa);
                                 vv = fma((double)v, (double)v, vv);
-                                node_rec<4>(W, r)[a] = wa;
+                                node_rec<WS>(W, r)[a] = wa;
                                 // the displacement update of the next pass
                                 qn[a] = n0.q[a];
                                 cn[a] = n0.c[a];

@@ -102,7 +102,9 @@ struct SolveArgs {
                               //   (FP32, 32 B per node); the state after pass k
                               //   is in buffer k & 1
     int64_t qhalf;            // doubles per state buffer (4 * nodes)
-    double *wbuf;             // [nodes * 4] running half-step velocities
+    double *wbuf;             // [nodes * 4] running half-step velocities (24 B per
+                              //   node in FP64, 16 B in FP32; the launch-loop
+                              //   comparator uses 32 B records)
     double *F_cur;            // [P * 9] F of the current solve
     double *F_last;           // [P * 9] F of the last finished solve
     int32_t *has_state;       // [P] 1 once a solve has finished
