@@ -181,7 +181,7 @@ def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
 
     from paper_2305_07030_amd import serve as SV
     dev = SV.PoolDevice(batch, tol=1e-8, damping=beta, dt_safety=0.9)
-    budget = SV.STATE_BYTES_PER_NODE * int(sum(n.n_nodes for n in batch.nets))
+    budget = SV.state_bytes_per_node() * int(sum(n.n_nodes for n in batch.nets))
 
     def mk():
         return SV.Server(dev, hbm_budget_bytes=budget, max_slots=len(batch), tick_passes=4000)

@@ -99,7 +99,12 @@ typedef enum {
  *                       interleaved, finite; the network lives in the unit cube
  *   fiber_nodes         [total_fibers * 2] problem-local node ids (a, b), a != b
  *   EA                  [total_fibers] finite and > 0
- *   fixed               [total_nodes] 1 = prescribed node, 0 = free
+ *   fixed               [total_nodes] 1 = prescribed node, 0 = free; or NULL:
+ *                       then the band rule below decides
+ *   band                used when fixed is NULL (finite, >= 0): a node is
+ *                       prescribed iff it lies within `band` of a face of the
+ *                       unit cube, min_k min(X_k, 1 - X_k) <= band (inclusive);
+ *                       ignored when fixed is given
  * Each problem needs 1 .. 524288 nodes (the global-placement kernel keeps a
  * problem's 64-node slice headers in LDS), every free node needs >= 1 fiber
  * and every fiber a nonzero reference length.
@@ -112,6 +117,7 @@ typedef struct {
     const int32_t *fiber_nodes;
     const double *EA;
     const uint8_t *fixed;
+    double band;
 } dr_networks;
 
 /*
@@ -128,8 +134,11 @@ typedef struct {
  *               LDS, at most 8 nodes per thread)
  *   chunk       incidences per step of the force gather, whose loads are
  *               issued one step ahead: 0 = automatic, else 1, 2 or 4 (a
- *               tuning knob; results do not depend on it; global placement
- *               with 256 threads always uses 1)
+ *               tuning knob; results do not depend on it).  Global placement
+ *               with 256 threads runs chunks of 1 only: DR_PLACE_GLOBAL with
+ *               block 256 and chunk 2 or 4 is rejected (DR_E_INVALID); in the
+ *               automatic split the global class then runs chunks of 1
+ *               (dr_batch_class_info reports each class's chunk)
  *   stall_window  >= 0; 0 = off.  Otherwise a solve also ends (DR_STALLED)
  *               when its best residual has not improved by 0.1 % during the
  *               last stall_window passes.  Not part of the paper's loop: a
@@ -381,11 +390,21 @@ void dr_batch_destroy(dr_batch *b);
  *
  * dr_pool_create: a batch of the networks (as dr_batch_create) plus an empty
  * request queue.
- *   state_budget_bytes  cap on the running state of in-flight solves (64 B
- *                       per node of each), 0 = none
+ *   state_budget_bytes  cap on the running state of in-flight solves, 0 =
+ *                       none.  The running state of a solve is
+ *                       dr_state_bytes_per_node bytes per node of its network
+ *                       (two state records and one velocity record).  With a
+ *                       budget below that of all networks together, the pool
+ *                       allocates the running state as one device arena of
+ *                       state_budget_bytes and places each admitted solve in a
+ *                       contiguous run of it until the solve retires, so the
+ *                       budget bounds the device memory of in-flight solves
+ *                       (topology, masses and last displacements of every
+ *                       network stay resident: they are the pool)
  *   max_slots           cap on in-flight solves (>= 1)
  *   tick_passes         DR passes per poll for every in-flight solve (>= 1)
- * Errors: as dr_batch_create, DR_E_INVALID for the caps.
+ * Errors: as dr_batch_create, DR_E_INVALID for the caps (a budget below one
+ * node's running state).
  */
 typedef struct dr_pool dr_pool;
 dr_status dr_pool_create(const dr_networks *nets, const dr_options *opt, void *hip_stream,
@@ -405,7 +424,8 @@ dr_status dr_pool_submit(dr_pool *pool, int32_t id, const double *F, int64_t tag
 /*
  * One scheduling step: admits queued requests first come first served (a
  * request whose network is in flight waits without blocking the queue; one
- * that exceeds the slot or budget cap blocks it), runs one launch of
+ * that exceeds the slot or budget cap, or finds no free run of the arena
+ * long enough for its network, blocks it), runs one launch of
  * tick_passes passes over every in-flight solve (new ones start, the others
  * resume from their exact saved state: a result is the same bits as one
  * dr_solve with DR_START_WARM), waits for it, and retires the finished
@@ -426,6 +446,13 @@ dr_status dr_pool_status(const dr_pool *pool, int32_t *queued, int32_t *in_fligh
 
 /* Releases the pool and its batch (waits for its stream).  NULL is ignored. */
 void dr_pool_destroy(dr_pool *pool);
+
+/* Device bytes of running state that one node of an in-flight solve needs
+ * (the unit of a pool's state budget): 72 for DR_FP64 (two 24-byte state
+ * records and a 24-byte velocity record), 80 for DR_FP32 (two 32-byte state
+ * records and a 16-byte velocity record).  Host only.
+ * Errors: DR_E_INVALID (NULL bytes, unknown precision). */
+dr_status dr_state_bytes_per_node(int32_t precision, int64_t *bytes);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *dr_last_error(void);

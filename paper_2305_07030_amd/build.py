@@ -1,39 +1,68 @@
-"""Builds libdr.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree."""
+"""Builds libdr.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
+
+Each translation unit is compiled to an object of its own (in parallel: the
+persistent kernels are instantiated in several units so that no one unit
+holds all of them), then the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdr.so")
-SOURCES = [os.path.join(CSRC, "dr_host.cpp"), os.path.join(CSRC, "dr_kernels.hip")]
-HEADERS = [os.path.join(CSRC, "dr_layout.h"), os.path.join(ROOT, "include", "dr.h")]
+OBJDIR = os.path.join(ROOT, "_build", "libdr")
+SOURCES = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "dr_host.cpp")]
+HEADERS = sorted(glob.glob(os.path.join(CSRC, "*.h"))) + [os.path.join(ROOT, "include", "dr.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions stay off in every HIP build of this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into paper_2305_07030_amd/libdr.so (always rebuilds)."""
+def _filter(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
+def _compile(src: str):
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return src, obj, cmd, res.returncode, _filter(res.stdout + res.stderr)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source and link paper_2305_07030_amd/libdr.so (always rebuilds)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, os.cpu_count() or 1), 16)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_compile, SOURCES))
+    errors = []
+    for src, obj, cmd, rc, out in results:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        if rc != 0:
+            errors.append(f"hipcc failed on {os.path.basename(src)}:\n{out}")
+        elif verbose and out.strip():
+            print(out)
+    if errors:
+        raise RuntimeError("\n".join(errors))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + [r[1] for r in results]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
-                    if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError("link failed:\n" + _filter(res.stdout + res.stderr))
     os.replace(tmp, LIB)
     return LIB
 

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <cmath>
 #include <cstdarg>
@@ -55,6 +56,17 @@ dr_status fail(dr_status st, const char *fmt, ...)
 constexpr int kLdsLimit = 160 * 1024;
 constexpr int kMaxNpt = 8;
 
+// Running-state records of one in-flight solve, per node: two state buffers
+// (the state after pass k lives in buffer k & 1) of 3 doubles (FP64 position)
+// or 4 doubles (FP32 state and its compensation terms), and one half-step
+// velocity record of 3 doubles (FP64) or 2 (FP32: 4 floats).
+int64_t state_doubles(int precision) { return precision == DR_FP32 ? 4 : 3; }
+int64_t velocity_doubles(int precision) { return precision == DR_FP32 ? 2 : 3; }
+int64_t state_bytes_per_node(int precision)
+{
+    return 8 * (2 * state_doubles(precision) + velocity_doubles(precision));
+}
+
 // Host copy of one packed problem's node permutation (caller id -> local id).
 struct HostProblem {
     int32_t N, N_free, M;
@@ -71,6 +83,9 @@ struct dr_batch {
     int32_t P = 0;
     int64_t total_nodes = 0, total_fibers = 0, total_slices = 0, total_inc = 0;
     int32_t n_max = 0;
+    // running-state records (qbuf, wbuf): one per node of the batch, or a
+    // pool's arena of fewer records that in-flight solves are placed in
+    int64_t state_nodes = 0;
     std::vector<HostProblem> hp;
     std::vector<ProbDesc> desc;
     // device arrays: network
@@ -83,6 +98,7 @@ struct dr_batch {
     KL32 *d_kl32 = nullptr;
     // device arrays: state and results (per problem)
     double *d_u = nullptr, *d_qbuf = nullptr, *d_wbuf = nullptr;
+    int64_t *d_state_off = nullptr; // [P] first running-state record of each problem
     double *d_F_cur = nullptr, *d_F_last = nullptr;
     int32_t *d_has_state = nullptr, *d_status = nullptr;
     double *d_sigma = nullptr, *d_sigma_fib = nullptr, *d_rho = nullptr, *d_ke = nullptr;
@@ -104,6 +120,9 @@ struct dr_batch {
     double *h_F = nullptr;
     int32_t *h_ids = nullptr, *h_order = nullptr, *h_starts = nullptr;
     double *h_scalars = nullptr;
+    std::vector<int64_t> state_off; // host copy of d_state_off
+    int64_t *h_state_off = nullptr;  // pinned staging of it
+    bool state_off_dirty = false;    // changed since its last upload
     hipEvent_t staged = nullptr;
     // host mirror of which problems have a running solve (for DR_RESUME checks)
     std::vector<char> running;
@@ -143,11 +162,11 @@ void free_all(dr_batch *b)
                    b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
-                   b->d_e_work, b->d_e_damp};
+                   b->d_e_work, b->d_e_damp, b->d_state_off};
     if (!b->ws)
         for (void *p : dev)
             if (p) (void)hipFree(p);
-    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars};
+    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars, b->h_state_off};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     if (b->staged) (void)hipEventDestroy(b->staged);
@@ -217,8 +236,10 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
     if (!nets) return fail(DR_E_INVALID, "networks is NULL");
     const int32_t P = nets->n_problems;
     if (P < 1) return fail(DR_E_INVALID, "n_problems must be >= 1 (got %d)", P);
-    if (!nets->node_offsets || !nets->fiber_offsets || !nets->X || !nets->EA || !nets->fixed)
+    if (!nets->node_offsets || !nets->fiber_offsets || !nets->X || !nets->EA)
         return fail(DR_E_INVALID, "a required network array is NULL");
+    if (!nets->fixed && !(nets->band >= 0.0 && std::isfinite(nets->band)))
+        return fail(DR_E_INVALID, "fixed is NULL and band (%g) is not finite and >= 0", nets->band);
     const bool fp32 = opt->precision == DR_FP32;
     const int64_t *no = nets->node_offsets, *fo = nets->fiber_offsets;
     if (no[0] != 0 || fo[0] != 0) return fail(DR_E_INVALID, "offsets must start at 0");
@@ -257,7 +278,19 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
         const double *X = nets->X + 3 * no[p];
         const int32_t *fib = nets->fiber_nodes + 2 * fo[p];
         const double *EA = nets->EA + fo[p];
-        const uint8_t *fixed = nets->fixed + no[p];
+        // prescribed nodes: the caller's mask, or the band rule (a node within
+        // `band` of a face of the unit cube, inclusive)
+        std::vector<uint8_t> band_mask;
+        if (!nets->fixed) {
+            band_mask.resize(N);
+            for (int32_t i = 0; i < N; ++i) {
+                double dmin = 1.0;
+                for (int a = 0; a < 3; ++a)
+                    dmin = std::min(dmin, std::min(X[3 * i + a], 1.0 - X[3 * i + a]));
+                band_mask[i] = dmin <= nets->band ? 1 : 0;
+            }
+        }
+        const uint8_t *fixed = nets->fixed ? nets->fixed + no[p] : band_mask.data();
 
         // L2g: L^2 rounded as the kernels form squared lengths,
         // fma(dz, dz, fma(dy, dy, dx * dx)), so that l^2 - L^2 is exactly 0
@@ -499,12 +532,14 @@ dr_status create_device(dr_batch *b, Packed &pk)
     UP(d_kl, kl)
     UP(d_kl32, kl32)
 #undef UP
+    if ((s = dev_upload(b, &b->d_state_off, b->state_off, st)) != DR_OK) return s;
     const size_t P = (size_t)b->P, nodes = (size_t)b->total_nodes;
+    const size_t rec = (size_t)b->state_nodes;
 #define ZS(dst, n)                                                                                \
     if ((s = dev_zeros(b, &b->dst, (n), st)) != DR_OK) return s;
     ZS(d_u, 3 * nodes)
-    ZS(d_qbuf, 2 * 4 * nodes) // two state buffers
-    ZS(d_wbuf, 4 * nodes)
+    ZS(d_qbuf, 2 * (size_t)state_doubles(b->opt.precision) * rec) // two state buffers
+    ZS(d_wbuf, (size_t)velocity_doubles(b->opt.precision) * rec)
     ZS(d_F_cur, 9 * P)
     ZS(d_F_last, 9 * P)
     ZS(d_has_state, P)
@@ -527,7 +562,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
     if (b->opt.energy_tol > 0.0) ZS(d_enode, 4 * nodes)
     // with a caller-owned workspace the scatter comparator's force buffer is
     // carved up front (it is allocated on first use otherwise)
-    if (b->ws || b->counting) ZS(d_gscat, 4 * (size_t)std::max(pk.n_max, 1))
+    if (b->ws || b->counting) ZS(d_gscat, 3 * (size_t)std::max(pk.n_max, 1))
 #undef ZS
     if (b->counting) return DR_OK;
     const int rc = drk::launch_fill_i32(b->d_status, DR_IDLE, (int64_t)P, st);
@@ -537,6 +572,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_order), P * sizeof(int32_t), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_starts), P * sizeof(int32_t), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_scalars), 8 * sizeof(double), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_state_off), P * sizeof(int64_t), 0));
     HIPCHECK(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
     HIPCHECK(hipStreamSynchronize(st));
     return DR_OK;
@@ -577,7 +613,14 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     }
     pl.block = block ? block : 1024;
     pl.npt = 0;
-    // 256 threads: chunks of 1 only (the only global build of that width)
+    // 256 threads: chunks of 1 only (the only global build of that width);
+    // an explicit request for another chunk there is reported (npt = -2)
+    // when the placement was asked for, and replaced by 1 in the automatic
+    // split (dr_batch_class_info shows the chunk each class runs)
+    if (pl.block == 256 && opt.chunk > 1 && opt.placement == DR_PLACE_GLOBAL) {
+        pl.npt = -2;
+        return pl;
+    }
     pl.chunk = pl.block == 256 ? 1 : (opt.chunk ? opt.chunk : (pl.block == 1024 ? 1 : 2));
     // reduction area plus the slice-header table (16 B per slice)
     const int slices = (n_max + drk::kWave - 1) / drk::kWave; // <= kGlbHdrMax (validated)
@@ -617,6 +660,9 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         o.chunk = r.chunk;
         o.placement = r.placement;
         c.plan = plan_for(o, std::max(c.n_max, 1));
+        if (c.plan.npt == -2)
+            return fail(DR_E_INVALID, "class up to %d nodes: global placement with 256 threads "
+                        "runs gather chunks of 1 only (got %d)", r.n_hi, r.chunk);
         if (c.plan.npt < 0)
             return fail(DR_E_INVALID, "class up to %d nodes: DR_PLACE_LDS cannot hold %d nodes",
                         r.n_hi, c.n_max);
@@ -633,6 +679,9 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         c.n_max = mc.first;
         c.count = mc.second;
         c.plan = plan_for(b->opt, std::max(c.n_max, 1));
+        if (c.plan.npt == -2)
+            return fail(DR_E_INVALID, "global placement with 256 threads runs gather chunks of 1 only "
+                        "(got %d)", b->opt.chunk);
         if (c.plan.npt < 0)
             return fail(DR_E_INVALID, "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
                         c.n_max, b->opt.block);
@@ -661,6 +710,7 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         g.count = mc.second;
         dr_options o = b->opt;
         o.placement = DR_PLACE_GLOBAL;
+        if (o.block == 256) o.chunk = 1; // the only global build of that width
         g.plan = plan_for(o, std::max(g.n_max, 1));
         cls.push_back(g);
     }
@@ -722,8 +772,9 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.kl = b->d_kl;
     a.kl32 = b->d_kl32;
     a.u = b->d_u;
+    a.state_off = b->d_state_off;
     a.qbuf = b->d_qbuf;
-    a.qhalf = 4 * b->total_nodes;
+    a.qhalf = state_doubles(b->opt.precision) * b->state_nodes;
     a.wbuf = b->d_wbuf;
     a.F_cur = b->d_F_cur;
     a.F_last = b->d_F_last;
@@ -816,6 +867,12 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
     if (starts)
         HIPCHECK(hipMemcpyAsync(b->d_starts, b->h_starts, sizeof(int32_t) * (size_t)n_ids,
                                 hipMemcpyHostToDevice, b->stream));
+    if (b->state_off_dirty) {
+        std::memcpy(b->h_state_off, b->state_off.data(), sizeof(int64_t) * (size_t)b->P);
+        HIPCHECK(hipMemcpyAsync(b->d_state_off, b->h_state_off, sizeof(int64_t) * (size_t)b->P,
+                                hipMemcpyHostToDevice, b->stream));
+        b->state_off_dirty = false;
+    }
     HIPCHECK(hipEventRecord(b->staged, b->stream));
     return DR_OK;
 }
@@ -890,12 +947,23 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
 // is one dr_advance launch over the in-flight requests (new ones start warm
 // from the network's previous solve, the others resume) with a fixed pass
 // budget; finished solves retire into a completion queue.
+//
+// With a state budget, the running state of in-flight solves (two state
+// records and one velocity record per node) lives in a device arena of
+// budget / state_bytes_per_node records: a request is admitted only when a
+// contiguous run of records for its network is free, keeps that run until it
+// retires, and the arena is all the running-state memory the pool has.
+// What stays resident for every network is its topology, masses and the
+// displacements of its last solve (the warm start).
 // ---------------------------------------------------------------------------
 struct dr_pool {
     dr_batch *b = nullptr;
     int32_t P = 0;
     std::vector<int64_t> nodes; // per network
     int64_t state_budget = 0;   // bytes of running state in flight; 0 = unlimited
+    int64_t bytes_per_node = 0; // running state of one node of an in-flight solve
+    int64_t arena = 0;          // records of the state arena; 0 = one per node of the pool
+    std::map<int64_t, int64_t> free_runs; // arena: first record -> length of a free run
     int32_t max_slots = 0;
     int64_t tick_passes = 0;
     struct Req {
@@ -906,6 +974,7 @@ struct dr_pool {
     struct Flight {
         Req r;
         bool started;
+        int64_t rec; // first arena record (arena > 0)
     };
     struct Done {
         int64_t tag;
@@ -921,9 +990,39 @@ struct dr_pool {
 };
 
 namespace {
-// Running state an in-flight solve keeps per node: the 32-byte state record
-// and the 32-byte velocity record.
-constexpr int64_t kPoolBytesPerNode = 64;
+
+// First fit: takes a run of n records from the arena's free runs.
+bool arena_take(dr_pool *pl, int64_t n, int64_t *first)
+{
+    for (auto it = pl->free_runs.begin(); it != pl->free_runs.end(); ++it) {
+        if (it->second < n) continue;
+        *first = it->first;
+        const int64_t rest = it->second - n, at = it->first + n;
+        pl->free_runs.erase(it);
+        if (rest > 0) pl->free_runs[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+// Returns a run to the arena, merged with free neighbours.
+void arena_give(dr_pool *pl, int64_t first, int64_t n)
+{
+    auto next = pl->free_runs.lower_bound(first);
+    if (next != pl->free_runs.end() && next->first == first + n) {
+        n += next->second;
+        next = pl->free_runs.erase(next);
+    }
+    if (next != pl->free_runs.begin()) {
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == first) {
+            prev->second += n;
+            return;
+        }
+    }
+    pl->free_runs[first] = n;
+}
+
 } // namespace
 
 namespace {
@@ -932,13 +1031,17 @@ namespace {
 // dr_batch_create_in (device arrays carved from ws) and
 // dr_batch_workspace_bytes (counting: sizes only, no HIP call).
 dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_stream, char *ws,
-                      size_t ws_bytes, bool counting, dr_batch **out, size_t *bytes)
+                      size_t ws_bytes, bool counting, dr_batch **out, size_t *bytes,
+                      int64_t arena_nodes = 0)
 {
     dr_status s = validate_options(opt);
     if (s != DR_OK) return s;
     Packed pk;
     s = pack(nets, opt, pk);
     if (s != DR_OK) return s;
+    if (plan_for(*opt, pk.n_max).npt == -2)
+        return fail(DR_E_INVALID, "global placement with 256 threads runs gather chunks of 1 only "
+                    "(got %d)", opt->chunk);
     if (plan_for(*opt, pk.n_max).npt < 0)
         return fail(DR_E_INVALID, "placement DR_PLACE_LDS cannot hold a %d-node problem (block %d)",
                     pk.n_max, opt->block);
@@ -962,6 +1065,12 @@ dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_
     b->n_max = pk.n_max;
     b->desc = pk.desc;
     b->running.assign(b->P, 0);
+    // running-state records: each problem at its node_base, or (a pool's
+    // arena) placed when a solve is admitted
+    b->state_nodes = arena_nodes > 0 ? arena_nodes : b->total_nodes;
+    b->state_off.assign(b->P, 0);
+    if (arena_nodes <= 0)
+        for (int32_t p = 0; p < b->P; ++p) b->state_off[p] = pk.desc[p].node_base;
     b->hp = std::move(pk.hp);
     if (ws || counting) {
         // sizing pass (no HIP call), then the workspace check
@@ -1250,7 +1359,7 @@ dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n
         for (int32_t k = 0; k < n_ids; ++k)
             if ((s = check_F(F, k)) != DR_OK) return s;
         if (scatter && !b->d_gscat)
-            HIPCHECK(hipMalloc(&b->d_gscat, sizeof(double) * 4 * (size_t)std::max(b->n_max, 1)));
+            HIPCHECK(hipMalloc(&b->d_gscat, sizeof(double) * 3 * (size_t)std::max(b->n_max, 1)));
         if ((s = stage(b, F, ids, nullptr, n_ids)) != DR_OK) return s;
         SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
         a.order = nullptr;
@@ -1468,14 +1577,29 @@ dr_status dr_pool_create(const dr_networks *nets, const dr_options *opt, void *h
         if (max_slots < 1) return fail(DR_E_INVALID, "max_slots must be >= 1 (got %d)", max_slots);
         if (tick_passes < 1)
             return fail(DR_E_INVALID, "tick_passes must be >= 1 (got %lld)", (long long)tick_passes);
+        dr_status s = validate_options(opt);
+        if (s != DR_OK) return s;
+        if (!nets || nets->n_problems < 1 || !nets->node_offsets)
+            return fail(DR_E_INVALID, "networks is NULL or empty");
+        const int64_t bpn = state_bytes_per_node(opt->precision);
+        const int64_t total = nets->node_offsets[nets->n_problems];
+        // an arena only when the budget holds less than every network's state
+        int64_t arena = state_budget_bytes / bpn;
+        if (state_budget_bytes > 0 && arena < 1)
+            return fail(DR_E_INVALID, "state_budget_bytes %lld holds no node's running state (%lld B)",
+                        (long long)state_budget_bytes, (long long)bpn);
+        if (state_budget_bytes == 0 || arena >= total) arena = 0;
         dr_batch *b = nullptr;
-        dr_status s = dr_batch_create(nets, opt, hip_stream, &b);
+        s = create_impl(nets, opt, hip_stream, nullptr, 0, false, &b, nullptr, arena);
         if (s != DR_OK) return s;
         dr_pool *pl = new dr_pool();
         pl->b = b;
         pl->P = nets->n_problems;
         pl->nodes.resize(pl->P);
         for (int32_t p = 0; p < pl->P; ++p) pl->nodes[p] = nets->node_offsets[p + 1] - nets->node_offsets[p];
+        pl->bytes_per_node = bpn;
+        pl->arena = arena;
+        if (arena > 0) pl->free_runs[0] = arena;
         pl->state_budget = state_budget_bytes;
         pl->max_slots = max_slots;
         pl->tick_passes = tick_passes;
@@ -1497,7 +1621,7 @@ dr_status dr_pool_submit(dr_pool *pl, int32_t id, const double *F, int64_t tag)
         if (id < 0 || id >= pl->P) return fail(DR_E_INVALID, "network %d out of range [0, %d)", id, pl->P);
         dr_status s = check_F(F, 0);
         if (s != DR_OK) return s;
-        const int64_t need = kPoolBytesPerNode * pl->nodes[id];
+        const int64_t need = pl->bytes_per_node * pl->nodes[id];
         if (pl->state_budget > 0 && need > pl->state_budget)
             return fail(DR_E_INVALID, "network %d alone needs %lld state bytes, over the budget of %lld", id,
                         (long long)need, (long long)pl->state_budget);
@@ -1533,11 +1657,17 @@ dr_status dr_pool_poll(dr_pool *pl, int32_t max_out, int64_t *tags, int32_t *ids
                 pl->queue.pop_front();
                 continue;
             }
-            const int64_t need = kPoolBytesPerNode * pl->nodes[r.id];
+            const int64_t need = pl->bytes_per_node * pl->nodes[r.id];
             if ((int32_t)pl->active.size() >= pl->max_slots ||
                 (pl->state_budget > 0 && pl->bytes + need > pl->state_budget))
                 break;
-            pl->active[r.id] = dr_pool::Flight{r, false};
+            int64_t rec = 0;
+            if (pl->arena > 0) {
+                if (!arena_take(pl, pl->nodes[r.id], &rec)) break; // no free run long enough
+                pl->b->state_off[r.id] = rec;
+                pl->b->state_off_dirty = true;
+            }
+            pl->active[r.id] = dr_pool::Flight{r, false, rec};
             pl->bytes += need;
             pl->queue.pop_front();
         }
@@ -1572,7 +1702,8 @@ dr_status dr_pool_poll(dr_pool *pl, int32_t max_out, int64_t *tags, int32_t *ids
                 d.iters = it[k];
                 std::memcpy(d.sigma, &sig[9 * (size_t)k], sizeof(d.sigma));
                 pl->done.push_back(d);
-                pl->bytes -= kPoolBytesPerNode * pl->nodes[slot_ids[k]];
+                pl->bytes -= pl->bytes_per_node * pl->nodes[slot_ids[k]];
+                if (pl->arena > 0) arena_give(pl, f->second.rec, pl->nodes[slot_ids[k]]);
                 pl->active.erase(f);
             }
         }
@@ -1606,6 +1737,16 @@ dr_status dr_pool_status(const dr_pool *pl, int32_t *queued, int32_t *in_flight,
     if (in_flight) *in_flight = (int32_t)pl->active.size();
     if (completed) *completed = (int32_t)pl->done.size();
     if (state_bytes) *state_bytes = pl->bytes;
+    return DR_OK;
+}
+
+dr_status dr_state_bytes_per_node(int32_t precision, int64_t *bytes)
+{
+    g_err.clear();
+    if (!bytes) return fail(DR_E_INVALID, "bytes is NULL");
+    if (precision != DR_FP64 && precision != DR_FP32)
+        return fail(DR_E_INVALID, "precision %d is not DR_FP64 or DR_FP32", precision);
+    *bytes = state_bytes_per_node(precision);
     return DR_OK;
 }
 

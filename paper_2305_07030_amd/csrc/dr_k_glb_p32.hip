@@ -1,0 +1,9 @@
+// Instantiates the global-placement DR kernel k_dr_glb<P32, BLOCK, C>.
+#include "dr_device.h"
+
+namespace drk {
+int launch_glb_p32(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)
+{
+    return launch_glb_all<P32>(a, pl, st);
+}
+} // namespace drk

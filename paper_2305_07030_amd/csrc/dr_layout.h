@@ -96,15 +96,16 @@ struct SolveArgs {
     const KL32 *kl32;         // [incidences] (FP32 state)
     // state kept on the device
     double *u;                // [nodes * 3] displacement of the last finished solve
-    double *qbuf;             // [2 * nodes * 4] running state, two buffers of qhalf
+    const int64_t *state_off; // [P] first record of the problem in qbuf / wbuf
+                              //   (its node_base, or its place in a pool's arena)
+    double *qbuf;             // [2 * qhalf] running state, two buffers of qhalf
                               //   doubles: positions (FP64, 24 B per node) or
                               //   displacements and their compensation terms
                               //   (FP32, 32 B per node); the state after pass k
                               //   is in buffer k & 1
-    int64_t qhalf;            // doubles per state buffer (4 * nodes)
-    double *wbuf;             // [nodes * 4] running half-step velocities (24 B per
-                              //   node in FP64, 16 B in FP32; the launch-loop
-                              //   comparator uses 32 B records)
+    int64_t qhalf;            // doubles per state buffer (3 or 4 per record)
+    double *wbuf;             // running half-step velocities (24 B per record in
+                              //   FP64, 16 B in FP32)
     double *F_cur;            // [P * 9] F of the current solve
     double *F_last;           // [P * 9] F of the last finished solve
     int32_t *has_state;       // [P] 1 once a solve has finished
@@ -135,7 +136,7 @@ struct LaunchPlan {
 // Implemented in dr_kernels.hip.
 int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream);
 // Launch-loop comparator: phase 0 set-up, 1 one gather pass, 3 one pass with
-// the zero + atomic-scatter force kernel (gbuf: 4 doubles per node), 2 finish.
+// the zero + atomic-scatter force kernel (gbuf: 3 doubles per node), 2 finish.
 int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, double *partial,
                         double *out_scalars, int64_t n_done, double rho, double ke, int status,
                         double *gbuf, void *stream);

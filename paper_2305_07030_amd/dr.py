@@ -30,7 +30,7 @@ EXPORTS = ("dr_options_default", "dr_batch_create", "dr_batch_workspace_bytes",
            "dr_solve_loop_scatter", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
            "dr_graph_launch", "dr_batch_destroy", "dr_pool_create", "dr_pool_submit", "dr_pool_poll",
-           "dr_pool_status", "dr_pool_destroy", "dr_last_error")
+           "dr_pool_status", "dr_pool_destroy", "dr_state_bytes_per_node", "dr_last_error")
 
 
 class DrError(RuntimeError):
@@ -46,7 +46,8 @@ class dr_networks(C.Structure):
                 ("X", C.POINTER(C.c_double)),
                 ("fiber_nodes", C.POINTER(C.c_int32)),
                 ("EA", C.POINTER(C.c_double)),
-                ("fixed", C.POINTER(C.c_uint8))]
+                ("fixed", C.POINTER(C.c_uint8)),
+                ("band", C.c_double)]
 
 
 class dr_options(C.Structure):
@@ -100,6 +101,8 @@ def load():
     lib.dr_pool_status.restype = C.c_int
     lib.dr_pool_destroy.argtypes = [vp]
     lib.dr_pool_destroy.restype = None
+    lib.dr_state_bytes_per_node.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
+    lib.dr_state_bytes_per_node.restype = C.c_int
     lib.dr_batch_workspace_bytes.argtypes = [C.POINTER(dr_networks), C.POINTER(dr_options),
                                              C.POINTER(C.c_size_t)]
     lib.dr_batch_workspace_bytes.restype = C.c_int
@@ -168,15 +171,18 @@ def make_options(**kw) -> dr_options:
 
 
 def pack_networks(packed: dict):
-    """dr_networks view of Batch.packed() arrays (the arrays are kept alive)."""
+    """dr_networks view of Batch.packed() arrays (the arrays are kept alive).
+    With packed["fixed"] None the library's band rule decides the prescribed
+    nodes (packed["band"])."""
     arrs = dict(
         node_offsets=np.ascontiguousarray(packed["node_offsets"], np.int64),
         fiber_offsets=np.ascontiguousarray(packed["fiber_offsets"], np.int64),
         X=np.ascontiguousarray(packed["X"], np.float64),
         fiber_nodes=np.ascontiguousarray(packed["fiber_nodes"], np.int32),
         EA=np.ascontiguousarray(packed["EA"], np.float64),
-        fixed=np.ascontiguousarray(packed["fixed"], np.uint8),
     )
+    if packed.get("fixed") is not None:
+        arrs["fixed"] = np.ascontiguousarray(packed["fixed"], np.uint8)
     n = dr_networks()
     n.n_problems = len(arrs["node_offsets"]) - 1
     n.node_offsets = arrs["node_offsets"].ctypes.data_as(C.POINTER(C.c_int64))
@@ -184,7 +190,9 @@ def pack_networks(packed: dict):
     n.X = arrs["X"].ctypes.data_as(C.POINTER(C.c_double))
     n.fiber_nodes = arrs["fiber_nodes"].ctypes.data_as(C.POINTER(C.c_int32))
     n.EA = arrs["EA"].ctypes.data_as(C.POINTER(C.c_double))
-    n.fixed = arrs["fixed"].ctypes.data_as(C.POINTER(C.c_uint8))
+    if "fixed" in arrs:
+        n.fixed = arrs["fixed"].ctypes.data_as(C.POINTER(C.c_uint8))
+    n.band = float(packed.get("band", 0.0))
     return n, arrs
 
 
@@ -331,6 +339,14 @@ def dr_graph_launch(h: int):
 
 def dr_batch_destroy(h: int):
     load().dr_batch_destroy(h)
+
+
+def state_bytes_per_node(precision: int = DR_FP64) -> int:
+    """Running-state bytes per node of an in-flight solve (the unit of a
+    serving pool's state budget)."""
+    v = C.c_int64()
+    _check(load().dr_state_bytes_per_node(int(precision), C.byref(v)))
+    return int(v.value)
 
 
 def dr_last_error() -> str:

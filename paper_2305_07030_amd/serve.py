@@ -33,9 +33,11 @@ import numpy as np
 
 from . import dr
 
-# Running state the device keeps per node of an in-flight solve: the 32-byte
-# state record and the 32-byte velocity record.
-STATE_BYTES_PER_NODE = 64
+
+def state_bytes_per_node(precision: int = dr.DR_FP64) -> int:
+    """Running state the device keeps per node of an in-flight solve (the
+    library's own figure: two state records and one velocity record)."""
+    return dr.state_bytes_per_node(precision)
 
 
 @dataclass
@@ -73,8 +75,10 @@ class ServeStats:
 
 class Server:
     def __init__(self, device, *, hbm_budget_bytes: int, max_slots: int, tick_passes: int,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, bytes_per_node: Optional[int] = None):
         self.dev = device
+        self.bytes_per_node = int(bytes_per_node or getattr(device, "bytes_per_node", 0)
+                                  or state_bytes_per_node())
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.tick_passes = int(tick_passes)
@@ -86,7 +90,7 @@ class Server:
         self.done: List[Request] = []
 
     def need_bytes(self, net: int) -> int:
-        return STATE_BYTES_PER_NODE * int(self.dev.node_count(net))
+        return self.bytes_per_node * int(self.dev.node_count(net))
 
     def submit(self, req: Request):
         if self.need_bytes(req.net) > self.budget:
@@ -241,6 +245,7 @@ class PoolDevice:
         self.batch = batch
         self.b = dr.DRBatch(batch, **opts)
         self.N = np.array([n.n_nodes for n in batch.nets])
+        self.bytes_per_node = state_bytes_per_node(opts.get("precision", dr.DR_FP64))
 
     def advance(self, ids, starts, budget, F):
         self.b.advance(ids, starts, budget, F=F)

@@ -174,3 +174,56 @@ def test_empty_batch_rejected(lib):
     with pytest.raises(dr.DrError) as e:
         dr.dr_batch_workspace_bytes(pk, dr.dr_options_default())
     assert e.value.status == dr.DR_E_INVALID and "n_problems" in str(e.value)
+
+
+def test_band_rule_when_fixed_is_null(lib):
+    """fixed = NULL: a node is prescribed iff it lies within `band` of a face
+    (inclusive).  Node 2 sits in the middle without a fiber: free (and
+    rejected) at band 0.02, prescribed (and accepted) at band 0.5; nodes 0
+    and 1 lie 0.01 from a face."""
+    X = np.array([[0.01, 0.5, 0.5], [0.99, 0.5, 0.5], [0.5, 0.5, 0.5]])
+    base = dict(node_offsets=np.array([0, 3], np.int64), fiber_offsets=np.array([0, 1], np.int64), X=X,
+                fiber_nodes=np.array([[0, 1]], np.int32), EA=np.ones(1), fixed=None)
+    o = dr.dr_options_default()
+    with pytest.raises(dr.DrError) as e:
+        dr.dr_batch_workspace_bytes(dict(base, band=0.02), o)
+    assert e.value.status == dr.DR_E_INVALID and "node 2 is free but has no fiber" in str(e.value)
+    n_band = dr.dr_batch_workspace_bytes(dict(base, band=0.5), o)
+    n_mask = dr.dr_batch_workspace_bytes(dict(base, fixed=np.ones(3, np.uint8)), o)
+    assert n_band == n_mask > 0
+    # exactly at the band distance counts as prescribed
+    with pytest.raises(dr.DrError):
+        dr.dr_batch_workspace_bytes(dict(base, band=0.4999), o)
+    assert dr.dr_batch_workspace_bytes(dict(base, band=0.5), o) > 0
+    for bad in (-0.1, float("nan"), float("inf")):
+        with pytest.raises(dr.DrError) as e:
+            dr.dr_batch_workspace_bytes(dict(base, band=bad), o)
+        assert e.value.status == dr.DR_E_INVALID and "band" in str(e.value)
+    # the band rule on a workload network gives the generator's mask
+    pk = I.small_batch(2, 300, 400, 0.01, seed=5).packed()
+    assert dr.dr_batch_workspace_bytes(dict(pk, fixed=None, band=I.BAND), o) == \
+        dr.dr_batch_workspace_bytes(pk, o)
+
+
+def test_state_bytes_per_node(lib):
+    """Two state records and one velocity record per node: 2 x 24 + 24 in
+    FP64, 2 x 32 + 16 in FP32."""
+    assert dr.state_bytes_per_node(dr.DR_FP64) == 72
+    assert dr.state_bytes_per_node(dr.DR_FP32) == 80
+    with pytest.raises(dr.DrError):
+        dr.state_bytes_per_node(7)
+
+
+def test_global_256_threads_runs_chunks_of_one(lib):
+    """Global placement with 256 threads has only a chunk-1 build: asking for
+    chunks of 2 or 4 there is an error, not a silent substitution."""
+    pk = _packed()
+    for ch in (2, 4):
+        o = dr.dr_options_default()
+        o.placement, o.block, o.chunk = dr.DR_PLACE_GLOBAL, 256, ch
+        with pytest.raises(dr.DrError) as e:
+            dr.dr_batch_workspace_bytes(pk, o)
+        assert e.value.status == dr.DR_E_INVALID and "chunks of 1" in str(e.value)
+    o = dr.dr_options_default()
+    o.placement, o.block, o.chunk = dr.DR_PLACE_GLOBAL, 256, 1
+    assert dr.dr_batch_workspace_bytes(pk, o) > 0

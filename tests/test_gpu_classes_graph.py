@@ -157,33 +157,47 @@ def test_tuned_plans_apply_and_match_oracle(tmp_path):
         assert rel(g["sigma"][i], o.sigma) < 1e-8
 
 
-def test_all_launch_shapes_same_bits():
+SHAPES = [(place, blk, ch) for place in (dr.DR_PLACE_LDS, dr.DR_PLACE_GLOBAL)
+          for blk in (256, 512, 1024) for ch in (1, 2, 4)]
+
+
+@pytest.fixture(scope="module")
+def shapes_reference():
+    rng = np.random.default_rng(64)
+    nets = [I.draw_network(rng, n) for n in (120, 300, 900, 2600)]
+    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
+    ref = dr.DRBatch(batch, tol=1e-300, max_iter=300, damping=1e-3, block=1024, chunk=1,
+                     placement=dr.DR_PLACE_LDS)
+    ref.solve()
+    R = ref.results(want_u=True)
+    ref.close()
+    assert (R["result"] == dr.DR_MAX_ITER).all()
+    return batch, R
+
+
+@pytest.mark.parametrize("place,blk,ch", SHAPES)
+def test_all_launch_shapes_same_bits(shapes_reference, place, blk, ch):
     """Every launch shape computes the same per-node arithmetic in the same
     order, so after a fixed pass count the states agree bit for bit across
     blocks, gather chunks and placements (sizes span one to several rows of
     slices per wave)."""
-    rng = np.random.default_rng(64)
-    nets = [I.draw_network(rng, n) for n in (120, 300, 900, 2600)]
-    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
-    K = 300
-    ref = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=1e-3, block=1024, chunk=1,
-                     placement=dr.DR_PLACE_LDS)
-    ref.solve()
-    R = ref.results(want_u=True)
-    assert (R["result"] == dr.DR_MAX_ITER).all()
-    for place in (dr.DR_PLACE_LDS, dr.DR_PLACE_GLOBAL):
-        for blk in (256, 512, 1024):
-            for ch in (1, 2, 4):
-                try:
-                    b = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=1e-3, block=blk, chunk=ch,
-                                   placement=place)
-                except dr.DrError as e:
-                    assert place == dr.DR_PLACE_LDS and e.status == dr.DR_E_INVALID
-                    continue
-                b.solve()
-                g = b.results(want_u=True)
-                say(f"placement {place} block {blk} chunk {ch}: status {g['result'].tolist()}")
-                assert (g["result"] == dr.DR_MAX_ITER).all()
-                assert np.array_equal(g["u"], R["u"]), (place, blk, ch)
-                assert np.array_equal(g["sigma"], R["sigma"]), (place, blk, ch)
-                b.close()
+    if place == dr.DR_PLACE_GLOBAL and blk == 256 and ch > 1:
+        pytest.skip("global placement with 256 threads has only a chunk-1 build (its chunk-2 and "
+                    "chunk-4 builds gave wrong states on multi-row problems and are not instantiated; "
+                    "the library rejects these plans)")
+    batch, R = shapes_reference
+    try:
+        b = dr.DRBatch(batch, tol=1e-300, max_iter=300, damping=1e-3, block=blk, chunk=ch,
+                       placement=place)
+    except dr.DrError as e:
+        assert place == dr.DR_PLACE_LDS and e.status == dr.DR_E_INVALID
+        pytest.skip("DR_PLACE_LDS cannot hold the largest network at this block")
+    cls = b.classes()
+    assert all(c["chunk"] == ch and c["block"] == blk for c in cls), cls
+    b.solve()
+    g = b.results(want_u=True)
+    say(f"placement {place} block {blk} chunk {ch}: status {g['result'].tolist()}")
+    assert (g["result"] == dr.DR_MAX_ITER).all()
+    assert np.array_equal(g["u"], R["u"]), (place, blk, ch)
+    assert np.array_equal(g["sigma"], R["sigma"]), (place, blk, ch)
+    b.close()

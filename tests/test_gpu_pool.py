@@ -39,7 +39,7 @@ def test_pool_matches_sequential_warm_solves():
             F[p] = F[p] + np.array([[e[0], e[1], e[2]], [e[1], e[3], e[4]], [e[2], e[4], e[5]]])
             reqs.append((int(p), F[p].copy()))
     nodes = np.array([n.n_nodes for n in batch.nets])
-    budget = int(64 * np.sort(nodes)[-3:].sum())  # about three of the largest in flight
+    budget = int(dr.state_bytes_per_node() * np.sort(nodes)[-3:].sum())  # about three of the largest in flight
     pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=4, tick_passes=300, **kw)
     for tag, (p, Fp) in enumerate(reqs):
         pool.submit(p, Fp, tag)
@@ -76,7 +76,7 @@ def test_pool_matches_sequential_warm_solves():
 
 def test_pool_rejections():
     batch = I.small_batch(2, 60, 200, 0.02, seed=97)
-    pool = dr.Pool(batch, state_budget_bytes=64 * 10, max_slots=1, tick_passes=100)
+    pool = dr.Pool(batch, state_budget_bytes=dr.state_bytes_per_node() * 10, max_slots=1, tick_passes=100)
     with pytest.raises(dr.DrError):  # the network alone is over the budget
         pool.submit(0, np.eye(3), 0)
     with pytest.raises(dr.DrError):

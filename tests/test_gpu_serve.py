@@ -34,7 +34,7 @@ def pool():
 
 def server(batch, slots=12):
     dev = SV.PoolDevice(batch, tol=1e-8, damping=1e-3, dt_safety=0.9)
-    return SV.Server(dev, hbm_budget_bytes=SV.STATE_BYTES_PER_NODE * 10 ** 7, max_slots=slots,
+    return SV.Server(dev, hbm_budget_bytes=SV.state_bytes_per_node() * 10 ** 7, max_slots=slots,
                      tick_passes=1500)
 
 

@@ -56,7 +56,7 @@ class FakeDevice:
 def make(sizes, need, budget_nodes, slots, tick=100):
     clock = FakeClock()
     dev = FakeDevice(sizes, need, clock)
-    srv = SV.Server(dev, hbm_budget_bytes=SV.STATE_BYTES_PER_NODE * budget_nodes,
+    srv = SV.Server(dev, hbm_budget_bytes=SV.state_bytes_per_node() * budget_nodes,
                     max_slots=slots, tick_passes=tick, clock=clock)
     return clock, dev, srv
 
@@ -74,9 +74,9 @@ def test_admission_limits_and_one_request_per_network():
         seen_slots = max(seen_slots, len(srv.active))
         for launch in dev.launches:
             assert len(set(launch)) == len(launch)
-        assert sum(sizes[p] for p in srv.active) * SV.STATE_BYTES_PER_NODE == srv.bytes_in_flight
+        assert sum(sizes[p] for p in srv.active) * SV.state_bytes_per_node() == srv.bytes_in_flight
     assert len(srv.done) == 30
-    assert seen_slots <= 3 and seen_bytes <= SV.STATE_BYTES_PER_NODE * 900
+    assert seen_slots <= 3 and seen_bytes <= SV.state_bytes_per_node() * 900
     # every request of a network ran after the previous one of that network
     by_net = {}
     for r in srv.done:
