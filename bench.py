@@ -68,16 +68,38 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """The host's CPU model and counts: os.cpu_count(), the CPUs this process
+    may run on, and the share used (the CPUs this process may use, at most 16:
+    the GPU hosts give each GPU's jobs a share of 16 cores)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity,
+            "used": max(1, min(16, affinity))}
+
+
 def cpu_baseline(batch, beta, tol, target_s=15.0):
     """The oracle, untuned, on a bounded sample: the first C networks, a fixed
-    number of DR passes each, one network per thread (C = host threads, at
-    most 16)."""
+    number of DR passes each, one network per thread (C = the host's CPU
+    share, see host_cpu)."""
     import numpy as np
 
     import oracle as O
     from concurrent.futures import ThreadPoolExecutor
     O.build(force=False)
-    C = max(1, min(16, os.cpu_count() or 1))
+    cpu = host_cpu()
+    C = cpu["used"]
     sub = batch.subset(range(min(C, len(batch))))
     # calibrate the pass count on one network
     t = time.perf_counter()
@@ -93,7 +115,65 @@ def cpu_baseline(batch, beta, tol, target_s=15.0):
     upd = sum(n.n_fibers * r.iters for n, r in zip(sub.nets, res))
     return {"value": upd / wall, "unit": "fiber-updates/s", "cores": C, "kind": "oracle",
             "sample": f"first {len(sub)} networks of the batch, {passes} DR passes each "
-                      f"(fixed pass count), one network per thread, {wall:.1f}s wall"}
+                      f"(fixed pass count), one network per thread, {wall:.1f}s wall",
+            "host": cpu}
+
+
+def loop_baseline(batch, beta, tol, stream, quantiles=(0.0, 0.25, 0.5, 0.75, 1.0)):
+    """The per-problem launch loop (the paper's naive design) on a stratified
+    sample: the networks at the given quantiles of the node count, each
+    solved to convergence (same tolerance and iteration as the batched
+    launch); rate = sum M n / sum t."""
+    import numpy as np
+
+    from paper_2305_07030_amd import dr
+    sizes = np.array([n.n_nodes for n in batch.nets])
+    order = np.argsort(sizes, kind="stable")
+    pick = sorted({int(order[min(len(order) - 1, int(round(q * (len(order) - 1))))]) for q in quantiles})
+    upd = wall = 0.0
+    rows = []
+    for i in pick:
+        lb = dr.DRBatch(batch.subset([i]), tol=tol, damping=beta, dt_safety=0.9, stream=stream.cuda_stream)
+        t = time.perf_counter()
+        lb.solve_loop()
+        r = lb.results()
+        dt = time.perf_counter() - t
+        lb.close()
+        m = batch.nets[i].n_fibers * int(r["iters"][0])
+        upd += m
+        wall += dt
+        rows.append({"network": i, "nodes": int(sizes[i]), "passes": int(r["iters"][0]),
+                     "seconds": round(dt, 3), "us_per_pass": round(dt / int(r["iters"][0]) * 1e6, 2)})
+        log(f"loop baseline: network {i} (N={sizes[i]}) {int(r['iters'][0])} passes in {dt:.2f}s")
+    return {"value": upd / wall, "unit": "fiber-updates/s",
+            "sample": f"networks at node-count quantiles {list(quantiles)} solved to convergence by the "
+                      f"per-problem launch loop; rate = sum M n / sum t",
+            "networks": rows}
+
+
+def ceilings():
+    """Measured copy bandwidths: a buffer pair that fits in the 256 MB
+    Infinity Cache (MALL) copied repeatedly, and one that does not (HBM)."""
+    import torch
+    out = {}
+    for name, mib, reps in (("mall_copy", 48, 200), ("hbm_copy", 2048, 10)):
+        x = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / 1e3
+        out[name + "_GBps"] = 2 * mib * (1 << 20) * reps / s / 1e9
+        out[name + "_bytes"] = 2 * mib * (1 << 20)
+        del x, y
+    log("ceilings:", out)
+    return out
 
 
 def fp32_leg(batch, stream, beta=1e-3):
@@ -483,6 +563,10 @@ def main():
                     help="uneven workload: also solve the batch to convergence")
     ap.add_argument("--converge-limit", type=float, default=900.0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tail-at", type=int, default=0,
+                    help="tail hand-off: problems left running when the rest move to group launches")
+    ap.add_argument("--tail-group", type=int, default=0,
+                    help="tail hand-off: workgroups per problem (0 = automatic)")
     ap.add_argument("--placement", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
@@ -521,7 +605,8 @@ def main():
     copy_calibration(args.copy_mib)
     stream = torch.cuda.current_stream()
     b = dr.DRBatch(batch, tol=tol, damping=beta, dt_safety=0.9, block=args.block,
-                   placement=args.placement, stream=stream.cuda_stream)
+                   placement=args.placement, tail_at=args.tail_at, tail_group=args.tail_group,
+                   stream=stream.cuda_stream)
     info = b.info()
     log("launch:", info)
     Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
@@ -552,6 +637,8 @@ def main():
     per_launch = updates / args.steps
     flops = FLOP_PER_UPDATE * per_launch / kern_s
     hbm_equiv = BYTES_PER_UPDATE * per_launch / kern_s
+    traffic = traffic_for(args.workload)
+    ceil = ceilings()
     out = {
         "metric": "fiber-element updates/s (batched persistent launch)",
         "value": value,
@@ -567,36 +654,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "networks": len(batch), "fibers": int(M.sum()),
                    "damping": beta, "dt_safety": 0.9, "block": info["block"],
+                   "tail_at": args.tail_at, "tail_group": args.tail_group,
                    "nodes_per_thread": info["nodes_per_thread"], "lds_bytes": info["lds_bytes"],
                    "passes_min": int(r["iters"].min()), "passes_max": int(r["iters"].max()),
                    "passes_median": int(np.median(r["iters"])), "converged": n_conv},
-        "roofline": {"bound": "alu", "achieved": flops / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / PEAK_FP64_VECTOR,
-                     "traffic": traffic_for(args.workload),
-                     "kernel": "k_dr_reg" if info["nodes_per_thread"] > 0 else "k_dr_glb",
+        # achieved = the method's algorithmic bytes (104 B per fiber-update,
+        # what the pass would move if the nodal state lived in HBM) per launch
+        # over the launch's time; traffic = bytes the launch really moves
+        # beyond L2 (rocprofv3 counters), far fewer: the state stays in LDS
+        "roofline": {"bound": "hbm", "achieved": hbm_equiv / 1e9, "peak": PEAK_HBM / 1e9,
+                     "unit": "GB/s", "frac": hbm_equiv / PEAK_HBM,
+                     "traffic": traffic,
+                     "achieved_is": "algorithmic bytes (104 B per fiber-update) / launch time",
+                     "kernel": ("k_dr_reg" if info["nodes_per_thread"] > 0 else "k_dr_glb") +
+                               (" + k_dr_glb group launch (tail hand-off)" if args.tail_at else ""),
                      "kernel_ms": kern_s * 1e3,
-                     "flop_per_update": FLOP_PER_UPDATE,
-                     "hbm_equivalent_GBps": hbm_equiv / 1e9,
-                     "hbm_equivalent_frac": hbm_equiv / PEAK_HBM},
+                     "bytes_per_update": BYTES_PER_UPDATE,
+                     "measured_beyond_l2_GBps": traffic / kern_s / 1e9 if traffic else None,
+                     "mall_copy_GBps": ceil["mall_copy_GBps"],
+                     "hbm_copy_GBps": ceil["hbm_copy_GBps"],
+                     "frac_of_mall_copy": hbm_equiv / 1e9 / ceil["mall_copy_GBps"],
+                     "fp64_alu_TFLOPs": flops / 1e12,
+                     "fp64_alu_frac": flops / PEAK_FP64_VECTOR,
+                     "flop_per_update": FLOP_PER_UPDATE},
     }
     if not args.no_loop:
-        sizes = np.array([n.n_nodes for n in batch.nets])
-        i = int(np.argmin(sizes))
-        lb = dr.DRBatch(batch.subset([i]), tol=tol, damping=beta, dt_safety=0.9,
-                        stream=stream.cuda_stream)
-        t = time.perf_counter()
-        lb.solve_loop()
-        lw = time.perf_counter() - t
-        lr = lb.results()
-        lupd = float(M[i] * lr["iters"][0])
-        out["loop_baseline"] = {"value": lupd / lw, "unit": "fiber-updates/s",
-                                "sample": f"network {i} (N={sizes[i]}, {int(M[i])} fibers) solved "
-                                          f"to convergence by the per-problem launch loop: "
-                                          f"{int(lr['iters'][0])} passes in {lw:.2f}s",
-                                "passes": int(lr["iters"][0]),
-                                "batched_passes": int(r["iters"][i]),
-                                "speedup_batched_over_loop": value / (lupd / lw)}
-        lb.close()
+        out["loop_baseline"] = loop_baseline(batch, beta, tol, stream)
+        out["loop_baseline"]["speedup_batched_over_loop"] = value / out["loop_baseline"]["value"]
         log("loop baseline:", out["loop_baseline"])
     if not args.no_loop and args.workload == "uniform":
         out["loop_multistream"] = multistream_leg(batch, beta)

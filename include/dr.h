@@ -71,7 +71,9 @@ typedef enum {
     DR_RUNNING = 3,   /* started by dr_advance and not finished yet */
     DR_IDLE = 4,      /* no solve has been started for this problem */
     DR_STALLED = 5,   /* rho made no 0.1 % progress for stall_window passes */
-    DR_ENERGY = 6     /* the energy balance check failed (energy_tol) */
+    DR_ENERGY = 6,    /* the energy balance check failed (energy_tol) */
+    DR_ABORTED = 7    /* a group's barrier wait timed out (tail hand-off); the
+                         problem's state is lost: start it again */
 } dr_result;
 
 typedef enum { DR_FP64 = 0, DR_FP32 = 1 } dr_precision;
@@ -154,6 +156,22 @@ typedef struct {
  *               passes and to ~1e-3 later, so a useful tolerance is ~0.1.
  *               Costs 32 B of traffic per free node per pass; dr_energy
  *               reports W and D.
+ *   tail_at     0..256; 0 = off.  Tail hand-off (section III: sub-problems
+ *               converge at different rates, which leaves a launch waiting
+ *               for its slowest ones): once at most tail_at problems of a
+ *               launch are still running, each of them saves its exact state
+ *               at its next check (every 256 passes) and a cooperative launch
+ *               of the same call finishes them with tail_group workgroups per
+ *               problem (global placement; the members of a group meet at a
+ *               barrier in device memory every pass).  Every node's
+ *               arithmetic is the same as in one workgroup; only the residual
+ *               norms are summed in another order, which could move the
+ *               stopping pass only if their last bits decided the test.
+ *               Not used under dr_graph_capture.
+ *   tail_group  0 = automatic (the most workgroups per problem, up to 16, that
+ *               let tail_at problems be resident at once), else 2..16;
+ *               DR_E_INVALID at creation when tail_at x tail_group workgroups
+ *               cannot be resident at once.
  */
 typedef struct {
     int32_t precision;
@@ -166,11 +184,13 @@ typedef struct {
     int32_t chunk;
     int64_t stall_window;
     double energy_tol;
+    int32_t tail_at;
+    int32_t tail_group;
 } dr_options;
 
 /* Fills *opt with the defaults: FP64, tol 1e-8, max_iter 2000000,
  * damping 1e-3, dt_safety 0.9, block 0, placement DR_PLACE_AUTO, chunk 0,
- * stall_window 0, energy_tol 0. */
+ * stall_window 0, energy_tol 0, tail_at 0, tail_group 0. */
 void dr_options_default(dr_options *opt);
 
 /*

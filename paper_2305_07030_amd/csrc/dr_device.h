@@ -49,6 +49,13 @@ namespace drk {
 enum { kConverged = 0, kMaxIter = 1, kNonFinite = 2 };
 // passes between two energy-balance checks
 constexpr int kEnergyEvery = 1024;
+// passes between two checks of how many problems of a launch still run
+// (the tail hand-off); divides kEnergyEvery
+constexpr int kDrainEvery = 256;
+// LDS slot (in wave 0's reduction record) of the hand-off decision:
+// doubles 4.. of each record hold the register variant's row headers
+constexpr int kDrainSlotReg = 3;
+constexpr int kDrainSlotGlb = 4;
 
 // Progress of a running solve for the optional stall guard.
 struct Progress {
@@ -873,9 +880,26 @@ __device__ __forceinline__ void record(const SolveArgs &A, const Slot &S, int64_
     A.rho[S.p] = rho;
     A.ke[S.p] = ke;
     A.status[S.p] = status;
-    if (status != kStatusRunning) {
+    if (status != kStatusRunning && status != kStatusAborted) {
         for (int k = 0; k < 9; ++k) A.F_last[9 * (int64_t)S.p + k] = S.F[k];
         A.has_state[S.p] = 1;
+    }
+}
+
+// End of a problem's part of a launch with the tail hand-off on (thread 0
+// writes): a solve drained to the group launch joins the tail list (with
+// the pass count its launch started at, from which the budget counts); any
+// other leaves the count of the launch's problems still running.
+__device__ __forceinline__ void launch_done(const SolveArgs &A, const Slot &S, int64_t n_start,
+                                            bool drained)
+{
+    if (A.tail_at <= 0) return;
+    if (drained) {
+        const int k = __hip_atomic_fetch_add(A.tail_count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        A.tail_list[k] = S.p;
+        A.n_begin[S.p] = n_start;
+    } else {
+        __hip_atomic_fetch_add(A.live, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -904,11 +928,10 @@ __device__ __forceinline__ void energy_sum_reg(const SolveArgs &A, int64_t nb, i
     }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void energy_sum_glb(const SolveArgs &A, int64_t nb, int Nf, int t,
+__device__ __forceinline__ void energy_sum_glb(const SolveArgs &A, int64_t nb, int Nf, int t, int stride,
                                                double (&e)[4])
 {
-    for (int r = t; r < Nf; r += BLOCK) {
+    for (int r = t; r < Nf; r += stride) {
         const double *x = A.enode + 4 * (nb + r);
         e[0] += x[0];
         e[1] += x[1];
@@ -928,7 +951,10 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
     const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
     // a resume of a solve that is not running is a no-op (uniform per workgroup)
-    if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
+    if (S.start == kResume && A.status[S.p] != kStatusRunning) {
+        if (tid == 0) launch_done(A, S, 0, false);
+        return;
+    }
     const Aff32 af = make_aff32(S.F);
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
@@ -1030,6 +1056,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     const double tol2 = A.tol * A.tol;
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
+    bool drained = false;
     Progress pg{__builtin_huge_val(), n};
     const bool has_free = wave_has_free(wave, Nf), has_pres = wave_has_prescribed<BLOCK>(wave, Nf, N);
     if (S.start == kResume) {
@@ -1118,8 +1145,16 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             }
         }
         wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres);
+        // every kDrainEvery passes thread 0 reads how many problems of the
+        // launch are still running; all threads read its decision after the
+        // barrier (before any later block sum reuses the slot)
+        const bool drain_pass = A.tail_at > 0 && ((n + 1) & (kDrainEvery - 1)) == 0;
+        if (drain_pass && tid == 0)
+            red[kDrainSlotReg] = __hip_atomic_load(A.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                                         A.tail_at ? 1.0 : 0.0;
         __syncthreads();
         block_totals2<NW>(red, lane, gf2, gb2);
+        const bool drain_now = drain_pass && red[kDrainSlotReg] != 0.0;
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
@@ -1132,6 +1167,10 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
                 status = kStatusEnergy;
                 break;
             }
+        }
+        if (drain_now) {
+            drained = true; // the rest of this solve runs in a group launch
+            break;
         }
         if (n - n0 >= A.budget) break;
         advance_all(tp);
@@ -1183,19 +1222,118 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             }
         }
     }
-    if (tid == 0) record(A, S, n, rho, ke, status, pg);
+    if (tid == 0) {
+        record(A, S, n, rho, ke, status, pg);
+        launch_done(A, S, n0, drained);
+    }
+}
+
+// Workgroup groups.  A problem too slow for one compute unit (a large
+// network, or the last networks of a batch still running) is shared by G
+// workgroups of a cooperative launch, co-resident by construction.  The
+// group works as one virtual workgroup of G * BLOCK threads: member m owns
+// the nodes i * G * BLOCK + m * BLOCK + tid, i.e. the same node -> row ->
+// wave layout as one workgroup of G * BLOCK threads, so every node's
+// arithmetic is the same as in the other kernels.  Once per pass the
+// members meet at a barrier in device memory: thread 0 of each posts its
+// workgroup's partial sums, releases its writes (agent scope), counts itself
+// in and waits for the other members, then acquires; every thread then sums
+// the G partials in member order (the same lanes and order in every wave of
+// every member, so all take the same stop decision).  The wait is bounded:
+// a member that waits longer than kGroupTimeoutTicks marks the group
+// aborted and every member leaves its loop, so every kernel ends.
+struct GroupCtx {
+    uint32_t *bar;  // arrival counter of the group (0 at the launch)
+    int32_t *abort; // nonzero once a member's wait timed out
+    double *part;   // [2][kGroupMax][4] partial sums by barrier parity and member
+    int G, member;
+    uint32_t nbar;  // group barriers passed in this launch
+};
+
+// 2 s of the 100 MHz wall clock.
+constexpr uint64_t kGroupTimeoutTicks = 200000000ull;
+
+// Barrier of the group's members; false when the group was aborted.  Every
+// thread calls it; flag is an LDS word of the workgroup.
+__device__ __forceinline__ bool group_barrier(GroupCtx &gc, int *flag)
+{
+    __syncthreads(); // the workgroup's writes of this phase are done
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(gc.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (gc.nbar + 1u) * (uint32_t)gc.G;
+        int ok = 1;
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(gc.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(gc.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > kGroupTimeoutTicks) {
+                __hip_atomic_store(gc.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *flag = ok;
+    }
+    __syncthreads();
+    ++gc.nbar;
+    return *flag != 0;
+}
+
+// Sums K <= 4 workgroup totals (equal in every thread of a member) over the
+// group's members in member order; every thread of every member gets the
+// same bits.  Returns false when the group was aborted.
+template <int K>
+__device__ __forceinline__ bool group_sum(GroupCtx &gc, int *flag, int lane, double (&v)[K])
+{
+    static_assert(K <= 4, "at most 4 sums per barrier");
+    double *mine = gc.part + ((gc.nbar & 1u) * kGroupMax + gc.member) * 4;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) mine[k] = v[k];
+    const bool ok = group_barrier(gc, flag);
+    const double *all = gc.part + ((gc.nbar - 1u) & 1u) * kGroupMax * 4;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // member m's value in lane m (G <= 16: one 16-lane row), zeros elsewhere
+        double t = 0.0;
+        if (lane < gc.G) t = __hip_atomic_load(all + lane * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v[k] = lane0(row_sum(t));
+    }
+    return ok;
+}
+
+// Whether the nodes r = i VB + base + lane (i >= 0, r < N) of a wave whose
+// first node is base include prescribed ones (Nf <= r < N); VB = threads of
+// the (virtual) workgroup.
+__device__ __forceinline__ bool wave_has_prescribed_vb(int base, int VB, int Nf, int N)
+{
+    int i = Nf - base - (kWave - 1); // first i whose 64 nodes reach Nf
+    i = i <= 0 ? 0 : (i + VB - 1) / VB;
+    return Nf < N && i * VB + base <= N - 1;
 }
 
 // ---------------------------------------------------------------------------
 // Global-placement variant: state and half-step velocities in device memory
 // (L2-resident for one problem), any problem size.
 //
-// The gather of a pass walks each wave's rows (slices i*NW + wave) as one
-// stream of chunks of C incidences in a two-stage software pipeline: while
-// chunk c is formed, the neighbour states of chunk c+1 and the topology of
-// chunk c+2 are in flight, and a row's own node data (state, degree, mass,
-// velocity) is loaded when its first chunk enters the pipeline.  The slice
-// headers sit in LDS when the problem has at most kGlbHdrMax slices.
+// The gather of a pass walks each wave's rows as one stream of chunks of C
+// incidences in a two-stage software pipeline: while chunk c is formed, the
+// neighbour states of chunk c+1 and the topology of chunk c+2 are in
+// flight, and a row's own node data (state, degree, mass, velocity) is
+// loaded when its first chunk enters the pipeline.  The slice headers of
+// the workgroup's rows sit in LDS.
+//
+// GRP = false: one workgroup per slot (blockIdx).  GRP = true: G workgroups
+// per problem (A.group), the problems taken from the tail list that the
+// preceding launch of the batch filled (A.tail_list / A.tail_count); the
+// members of one group are blockIdx values of one residue modulo 8, i.e.
+// one XCD (workgroups are dealt to the 8 XCDs round robin), so they share
+// that XCD's L2.
 // ---------------------------------------------------------------------------
 // A node's data for the force phase.
 template <class T> struct NodeData {
@@ -1206,22 +1344,54 @@ template <class T> struct NodeData {
     double m;
 };
 
-template <class Prec, int BLOCK, int C>
+template <class Prec, int BLOCK, int C, bool GRP = false>
 __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
 {
     using T = typename Prec::T;
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
-    const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
+    // reduction records, a flag word for the group barrier, then the slice headers
+    double *red = smem;
+    int *gflag = reinterpret_cast<int *>(smem + NW * kRedStride);
+    RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride + 2);
+    GroupCtx gc{nullptr, nullptr, nullptr, 1, 0, 0u};
+    Slot S;
+    if constexpr (GRP) {
+        const int b = blockIdx.x, G = A.group;
+        const int g = ((b >> 3) / G) * 8 + (b & 7);
+        if (g >= *A.tail_count) return; // uniform per workgroup
+        gc.G = G;
+        gc.member = (b >> 3) % G;
+        gc.bar = A.gbar + g;
+        gc.abort = A.gabort + g;
+        gc.part = A.gpart + (int64_t)g * 2 * kGroupMax * 4;
+        // a drained solve resumes from its saved state
+        S.slot = -1;
+        S.p = A.tail_list[g];
+        S.P = A.probs[S.p];
+        S.sb = A.state_off[S.p];
+        S.start = kResume;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) S.F[k] = A.F_cur[9 * (int64_t)S.p + k];
+    } else {
+        S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
+    }
     // a resume of a solve that is not running is a no-op (uniform per workgroup)
-    if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
+    if (S.start == kResume && A.status[S.p] != kStatusRunning) {
+        if (tid == 0 && gc.member == 0) launch_done(A, S, 0, false);
+        return;
+    }
     const Aff32 af = make_aff32(S.F);
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
-    double *red = smem;
     const int64_t nb = P.node_base;
     constexpr int QS = kQStride<T>;
+    // virtual workgroup: G members of BLOCK threads; this thread's virtual
+    // index and its wave's first node
+    const int VB = gc.G * BLOCK;
+    const int vt = gc.member * BLOCK + tid;
+    const int vbase = (gc.member * NW + wave) * kWave;
     // Two state buffers: the state after pass k lives in buffer k & 1, so a
     // pass can write each node's next state as soon as its velocity is known
     // while the other waves still read this pass's state (no separate
@@ -1235,15 +1405,23 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     T *W = reinterpret_cast<T *>(A.wbuf) + WS * S.sb;
     const T dt = (T)P.dt, hdt = (T)(0.5 * P.dt), cdamp = (T)P.c;
     using KLT = typename KLof<Prec>::type;
+    bool alive = true; // false once the group was aborted
 
-    // slice headers in LDS (the host admits at most kGlbHdrMax slices per
-    // problem and sizes the launch's LDS for the class's largest problem)
-    RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride);
-    for (int q = tid; q < P.n_slices; q += BLOCK)
-        hdr_lds[q] = RowHdr{(uint32_t)A.slice_off[P.slice_base + q], A.slice_w[P.slice_base + q]};
+    // headers of this workgroup's slices: row i of wave w is slice
+    // (i * G + member) * NW + w (the host admits at most kGlbHdrMax slices
+    // per problem and sizes the LDS for them)
+    {
+        const int rows = (P.n_slices + gc.G * NW - 1) / (gc.G * NW);
+        for (int t = tid; t < rows * NW; t += BLOCK) {
+            const int q = ((t / NW) * gc.G + gc.member) * NW + t % NW;
+            hdr_lds[t] = q < P.n_slices ? RowHdr{(uint32_t)A.slice_off[P.slice_base + q],
+                                                 A.slice_w[P.slice_base + q]}
+                                        : RowHdr{0, 0};
+        }
+    }
     const Topo<Prec> tpg = topo_of<Prec>(A, P);
-    // rows of this wave: i = 0 .. nrow-1 (node i*BLOCK + tid, slice i*NW + wave)
-    const int nrow = (N - wave * kWave + BLOCK - 1) / BLOCK;
+    // rows of this wave: i = 0 .. nrow-1 (node i * VB + vt)
+    const int nrow = N > vbase ? (N - vbase + VB - 1) / VB : 0;
     auto hdr_of = [&](int i) -> RowHdr { return uniform_hdr(hdr_lds + i * NW + wave); };
     // stream cursor: row i, first incidence k0 of the chunk, row width w;
     // i >= nrow = end of the stream
@@ -1265,7 +1443,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         pref_load<Prec, C>(tpg, hdr_of(x.i), x.k0, lane, pf);
     };
     auto node_data = [&](int i, NodeData<T> &nd) {
-        const int r = i * BLOCK + tid;
+        const int r = i * VB + vt;
         nd.q[0] = nd.q[1] = nd.q[2] = 0;
         nd.c[0] = nd.c[1] = nd.c[2] = 0;
         nd.w[0] = nd.w[1] = nd.w[2] = 0;
@@ -1284,19 +1462,26 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             }
         }
     };
+    // sums over the problem: the workgroup's (block_sum4, equal in all
+    // threads), then over the group's members
+    auto problem_sum4 = [&](double (&v)[4]) {
+        block_sum4<NW>(red, lane, wave, v);
+        if constexpr (GRP) alive = group_sum<4>(gc, gflag, lane, v) && alive;
+    };
 
     int64_t n = 0;
     if (S.start != kResume) {
-        for (int r = tid; r < N; r += BLOCK) {
+        for (int r = vt; r < N; r += VB) {
             T q[3];
             start_q<Prec>(A, S, r, q);
             pos.store(r, q[0], q[1], q[2]); // buffer 0: the state after pass 0
             if constexpr (Prec::kDisp)
                 for (int a = 0; a < 3; ++a) node_rec<QS>(qbase + 4, r)[a] = 0;
         }
-        if (tid == 0) begin_solve(A, S);
-        __syncthreads();
-        for (int r = tid; r < Nf; r += BLOCK) {
+        if (tid == 0 && gc.member == 0) begin_solve(A, S);
+        if constexpr (GRP) alive = group_barrier(gc, gflag);
+        else __syncthreads();
+        for (int r = vt; r < Nf; r += VB) {
             T qi[3], g[3];
             pos.load(r, qi[0], qi[1], qi[2]);
             gather<Prec, 4>(A, af, node_row(A, P, r), pos, lane, A.deg[nb + r], qi[0], qi[1], qi[2], g[0],
@@ -1321,11 +1506,15 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     __syncthreads();
 
     const int64_t n0 = n;
+    // passes this launch may make: the budget counts from the first launch
+    // of the batch call (a drained solve continues within the same budget)
+    const int64_t nlim = (GRP ? A.n_begin[S.p] : n0) + A.budget;
     const double tol2 = A.tol * A.tol;
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
+    bool drained = false;
     Progress pg{__builtin_huge_val(), n};
-    const bool has_free = wave_has_free(wave, Nf), has_pres = wave_has_prescribed<BLOCK>(wave, Nf, N);
+    const bool has_free = vbase < Nf, has_pres = wave_has_prescribed_vb(vbase, VB, Nf, N);
     if (S.start == kResume) {
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
@@ -1336,7 +1525,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     // nodes' states as they finish them.
     auto advance_from = [&](int64_t k) {
         const GlbQ<T> src{qbuf_of(k)}, dst{qbuf_of(k + 1)};
-        for (int r = tid; r < N; r += BLOCK) {
+        for (int r = vt; r < N; r += VB) {
             T q[3], c[3] = {0, 0, 0};
             src.load(r, q[0], q[1], q[2]);
             if constexpr (Prec::kDisp)
@@ -1350,8 +1539,9 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         }
     };
     advance_from(n);
-    __syncthreads();
-    for (;;) {
+    if constexpr (GRP) alive = group_barrier(gc, gflag) && alive;
+    else __syncthreads();
+    while (alive) {
         // pass n + 1 reads the state after pass n + 1's displacement update
         // (buffer (n + 1) & 1) and writes the next one into buffer n & 1;
         // the reduction slots alternate with the pass as well (one barrier
@@ -1399,7 +1589,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                 if (!c1_valid || c1_new_row) {
                     // c0 was the last chunk of its row: the node's damped
                     // acceleration, velocity updates and norm shares
-                    const int r = c0.i * BLOCK + tid;
+                    const int r = c0.i * VB + vt;
                     if (r < N) {
                         const double gg = sq3((double)g[0], (double)g[1], (double)g[2]);
                         if (r < Nf) {
@@ -1442,51 +1632,77 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             }
         }
         wave_partials2<NW>(red, lane, wave, gf2, gb2, has_free, has_pres, rslot);
+        // every kDrainEvery passes thread 0 reads how many problems of the
+        // launch are still running; all threads read its decision after the
+        // barrier
+        const bool drain_pass = !GRP && A.tail_at > 0 && ((n + 1) & (kDrainEvery - 1)) == 0;
+        if (drain_pass && tid == 0)
+            red[kDrainSlotGlb] = __hip_atomic_load(A.live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                                         A.tail_at ? 1.0 : 0.0;
         __syncthreads();
         block_totals2<NW>(red, lane, gf2, gb2, rslot);
+        const bool drain_now = drain_pass && red[kDrainSlotGlb] != 0.0;
+        if constexpr (GRP) {
+            double v[2] = {gf2, gb2};
+            if (!group_sum<2>(gc, gflag, lane, v)) { alive = false; break; }
+            gf2 = v[0]; gb2 = v[1];
+        }
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         if (A.energy_tol > 0.0 && n % kEnergyEvery == 0) {
             double e[4] = {0.0, 0.0, 0.0, ke2};
-            energy_sum_glb<BLOCK>(A, nb, Nf, tid, e);
-            block_sum4<NW>(red, lane, wave, e);
+            energy_sum_glb(A, nb, Nf, vt, VB, e);
+            problem_sum4(e);
             __syncthreads(); // its slots are read before the next pass writes any
-            double W, D;
-            energy_totals(P, e, false, W, D);
-            if (!energy_ok(A.energy_tol, 0.5 * e[3], W, D)) {
+            if (!alive) break;
+            double Wk, D;
+            energy_totals(P, e, false, Wk, D);
+            if (!energy_ok(A.energy_tol, 0.5 * e[3], Wk, D)) {
                 status = kStatusEnergy;
                 break;
             }
         }
-        if (n - n0 >= A.budget) break;
+        if (drain_now) {
+            drained = true; // the rest of this solve runs in a group launch
+            break;
+        }
+        if (n >= nlim) break;
     }
+    if (!alive) status = kStatusAborted;
     pos.base = qbuf_of(n); // the state after the last pass
     // kinetic energy of the last pass (reported only)
-    ke2 = block_sum1<NW>(red, lane, wave, ke2);
+    if (alive) {
+        double k4[4] = {ke2, 0.0, 0.0, 0.0};
+        problem_sum4(k4);
+        ke2 = k4[0];
+    }
     final_scalars(P, gf2, gb2, ke2, rho, ke);
-    if (A.energy_tol > 0.0) {
+    if (A.energy_tol > 0.0 && alive) {
         double e[4] = {0.0, 0.0, 0.0, 0.0};
-        energy_sum_glb<BLOCK>(A, nb, Nf, tid, e);
-        block_sum4<NW>(red, lane, wave, e);
-        double W, D;
-        energy_totals(P, e, status != kStatusRunning, W, D);
+        energy_sum_glb(A, nb, Nf, vt, VB, e);
+        problem_sum4(e);
+        double Wk, D;
+        energy_totals(P, e, status != kStatusRunning, Wk, D);
         if (status != kStatusRunning && status != kStatusEnergy && status != kNonFinite &&
-            !energy_ok(A.energy_tol, ke, W, D))
+            !energy_ok(A.energy_tol, ke, Wk, D))
             status = kStatusEnergy;
-        if (tid == 0) {
-            A.e_work[S.p] = W;
+        if (tid == 0 && gc.member == 0) {
+            A.e_work[S.p] = Wk;
             A.e_damp[S.p] = D;
         }
     }
 
-    if (status != kStatusRunning) {
-        for (int r = tid; r < N; r += BLOCK) {
+    if (status != kStatusRunning && status != kStatusAborted) {
+        for (int r = vt; r < N; r += VB) {
             T q[3];
             pos.load(r, q[0], q[1], q[2]);
             write_u<Prec>(A, S, r, q);
         }
     }
-    if (tid == 0) record(A, S, n, rho, ke, status, pg);
+    if (tid == 0 && gc.member == 0) {
+        record(A, S, n, rho, ke, status, pg);
+        launch_done(A, S, n0, drained);
+    }
 }
 
 
@@ -1557,6 +1773,39 @@ static inline int launch_glb(const SolveArgs &a, const LaunchPlan &pl, hipStream
         return launch(k_dr_glb<P, B, 2>, a.n_solve, B, pl.lds_bytes, st, a);
     }
 }
+
+// The group form of the global kernel, as a cooperative launch (the runtime
+// refuses a grid whose workgroups cannot all be resident at once).
+template <class P, int B, int C>
+static inline int launch_group(const SolveArgs &a, const LaunchPlan &pl, int grid, hipStream_t st)
+{
+    const void *k = reinterpret_cast<const void *>(k_dr_glb<P, B, C, true>);
+    if (pl.lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, pl.lds_bytes);
+        if (e != hipSuccess) return (int)e;
+    }
+    SolveArgs arg = a;
+    void *args[] = {&arg};
+    hipError_t e = hipLaunchCooperativeKernel(k, dim3(grid), dim3(B), args, (unsigned)pl.lds_bytes, st);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipGetLastError();
+}
+
+template <class P, int B, int C>
+static inline int group_occupancy(int lds_bytes, int *blocks_per_cu)
+{
+    const void *k = reinterpret_cast<const void *>(k_dr_glb<P, B, C, true>);
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return (int)e;
+    }
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, B, (size_t)lds_bytes);
+}
+
+int launch_group_p64(const SolveArgs &a, const LaunchPlan &pl, int grid, hipStream_t st);
+int launch_group_p32(const SolveArgs &a, const LaunchPlan &pl, int grid, hipStream_t st);
+int group_capacity_p64(int block, int lds_bytes, int *blocks_per_cu);
+int group_capacity_p32(int block, int lds_bytes, int *blocks_per_cu);
 
 template <class P>
 static inline int launch_glb_all(const SolveArgs &a, const LaunchPlan &pl, hipStream_t st)

@@ -110,6 +110,13 @@ struct dr_batch {
     double *d_partial = nullptr, *d_scalars = nullptr;
     double *d_gscat = nullptr; // forces of the atomic-scatter comparator (allocated on first use)
     double *d_enode = nullptr, *d_e_work = nullptr, *d_e_damp = nullptr; // energy balance
+    // tail hand-off: launch counters, the tail list, the groups' barriers
+    int32_t *d_live = nullptr, *d_tail_list = nullptr, *d_tail_count = nullptr, *d_gabort = nullptr;
+    uint32_t *d_gbar = nullptr;
+    int64_t *d_n_begin = nullptr;
+    double *d_gpart = nullptr;
+    int32_t tail_group = 0;     // workgroups per handed-off problem (0: hand-off off)
+    LaunchPlan tail_plan{};     // launch shape of the group kernel
     // caller-owned device workspace (dr_batch_create_in): every device array
     // is carved from it at 256-byte boundaries and never freed here;
     // `counting` is the sizing pass of dr_batch_workspace_bytes (no HIP call)
@@ -126,6 +133,7 @@ struct dr_batch {
     hipEvent_t staged = nullptr;
     // host mirror of which problems have a running solve (for DR_RESUME checks)
     std::vector<char> running;
+    std::vector<char> seen; // [P] scratch of the id checks (all zero between calls)
     // last dr_solve* call
     int32_t last_n = -1;
     std::vector<int32_t> last_ids;
@@ -162,7 +170,8 @@ void free_all(dr_batch *b)
                    b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
-                   b->d_e_work, b->d_e_damp, b->d_state_off};
+                   b->d_e_work, b->d_e_damp, b->d_state_off, b->d_live, b->d_tail_list,
+                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart};
     if (!b->ws)
         for (void *p : dev)
             if (p) (void)hipFree(p);
@@ -215,6 +224,10 @@ dr_status validate_options(const dr_options *o)
     if (o->stall_window < 0) return fail(DR_E_INVALID, "stall_window must be >= 0");
     if (!(o->energy_tol >= 0.0) || !std::isfinite(o->energy_tol))
         return fail(DR_E_INVALID, "energy_tol must be finite and >= 0 (got %g)", o->energy_tol);
+    if (o->tail_at < 0 || o->tail_at > drk::kTailMax)
+        return fail(DR_E_INVALID, "tail_at must be in [0, %d] (got %d)", drk::kTailMax, o->tail_at);
+    if (o->tail_group != 0 && (o->tail_group < 2 || o->tail_group > drk::kGroupMax))
+        return fail(DR_E_INVALID, "tail_group must be 0 or in [2, %d] (got %d)", drk::kGroupMax, o->tail_group);
     return DR_OK;
 }
 
@@ -560,6 +573,13 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_e_work, P)
     ZS(d_e_damp, P)
     if (b->opt.energy_tol > 0.0) ZS(d_enode, 4 * nodes)
+    ZS(d_live, 1)
+    ZS(d_tail_count, 1)
+    ZS(d_tail_list, drk::kTailMax)
+    ZS(d_gabort, drk::kTailMax)
+    ZS(d_gbar, drk::kTailMax)
+    ZS(d_n_begin, P)
+    ZS(d_gpart, (size_t)drk::kTailMax * 2 * drk::kGroupMax * 4)
     // with a caller-owned workspace the scatter comparator's force buffer is
     // carved up front (it is allocated on first use otherwise)
     if (b->ws || b->counting) ZS(d_gscat, 3 * (size_t)std::max(pk.n_max, 1))
@@ -576,6 +596,17 @@ dr_status create_device(dr_batch *b, Packed &pk)
     HIPCHECK(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
     HIPCHECK(hipStreamSynchronize(st));
     return DR_OK;
+}
+
+// LDS of the global kernel: the reduction records (20 doubles per wave), the
+// group barrier's flag word (16 B) and the slice headers (8 B each) of the
+// workgroup's rows, for a problem of n_max nodes shared by G workgroups.
+int glb_lds_bytes(int block, int G, int32_t n_max)
+{
+    const int nw = block / drk::kWave;
+    const int slices = (n_max + drk::kWave - 1) / drk::kWave; // <= kGlbHdrMax (validated)
+    const int rows = (slices + G * nw - 1) / (G * nw);
+    return nw * 20 * 8 + 16 + 8 * rows * nw;
 }
 
 // Launch shape for a batch whose largest problem has n_max nodes.  Returns
@@ -622,9 +653,7 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
         return pl;
     }
     pl.chunk = pl.block == 256 ? 1 : (opt.chunk ? opt.chunk : (pl.block == 1024 ? 1 : 2));
-    // reduction area plus the slice-header table (16 B per slice)
-    const int slices = (n_max + drk::kWave - 1) / drk::kWave; // <= kGlbHdrMax (validated)
-    pl.lds_bytes = (pl.block / drk::kWave) * 20 * 8 + 16 * slices;
+    pl.lds_bytes = glb_lds_bytes(pl.block, 1, n_max);
     return pl;
 }
 
@@ -747,9 +776,57 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
     return DR_OK;
 }
 
+// Launch shape of the tail hand-off's group kernel: 1024 threads per
+// workgroup, and as many workgroups per problem (tail_group, or automatic:
+// the most that let tail_at problems be co-resident, at most kGroupMax) as
+// the device holds.
+dr_status plan_tail(dr_batch *b)
+{
+    const int groups = b->opt.tail_at;
+    LaunchPlan pl{};
+    pl.block = 1024;
+    pl.npt = 0;
+    pl.chunk = 1;
+    pl.fp32 = b->opt.precision == DR_FP32;
+    int G = b->opt.tail_group;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int g_try = G > 0 ? G : 2;
+        pl.lds_bytes = glb_lds_bytes(pl.block, g_try, b->n_max);
+        int cap = 0;
+        const int rc = drk::group_grid_capacity(pl.fp32, pl.block, pl.lds_bytes, &cap);
+        if (rc != 0) return fail(DR_E_DEVICE, "group kernel occupancy: %s", drk::kernel_error_string(rc));
+        if (G == 0) {
+            // the largest G whose grid (whole rounds of 8 groups) fits
+            G = cap / (8 * ((groups + 7) / 8));
+            G = std::min(G, drk::kGroupMax);
+            if (G < 2)
+                return fail(DR_E_INVALID, "tail_at %d: the device holds %d group workgroups, too few for "
+                            "2 per problem", groups, cap);
+            continue; // size the LDS for this G
+        }
+        if (drk::group_grid(groups, G) > cap)
+            return fail(DR_E_INVALID, "tail_at %d x tail_group %d needs %d co-resident workgroups; the "
+                        "device holds %d", groups, G, drk::group_grid(groups, G), cap);
+        break;
+    }
+    pl.lds_bytes = glb_lds_bytes(pl.block, G, b->n_max);
+    b->tail_plan = pl;
+    b->tail_group = G;
+    return DR_OK;
+}
+
 SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
 {
     SolveArgs a{};
+    a.tail_at = 0; // set by launch_or_fail when the hand-off runs
+    a.live = b->d_live;
+    a.tail_list = b->d_tail_list;
+    a.tail_count = b->d_tail_count;
+    a.n_begin = b->d_n_begin;
+    a.group = b->tail_group;
+    a.gbar = b->d_gbar;
+    a.gabort = b->d_gabort;
+    a.gpart = b->d_gpart;
     a.probs = b->d_probs;
     a.ids = b->d_ids;
     a.order = b->d_order;
@@ -813,13 +890,23 @@ dr_status check_ids(dr_batch *b, const int32_t *ids, int32_t n_ids)
     if (!ids && n_ids != b->P)
         return fail(DR_E_INVALID, "ids is NULL but n_ids (%d) != n_problems (%d)", n_ids, b->P);
     if (ids) {
-        std::vector<char> seen(b->P, 0);
-        for (int32_t k = 0; k < n_ids; ++k) {
-            if (ids[k] < 0 || ids[k] >= b->P)
-                return fail(DR_E_INVALID, "ids[%d] = %d is out of range", k, ids[k]);
-            if (seen[ids[k]]) return fail(DR_E_INVALID, "ids[%d] = %d is repeated", k, ids[k]);
+        // the batch's preallocated marks, cleared again before returning
+        std::vector<char> &seen = b->seen;
+        dr_status s = DR_OK;
+        int32_t k = 0;
+        for (; k < n_ids; ++k) {
+            if (ids[k] < 0 || ids[k] >= b->P) {
+                s = fail(DR_E_INVALID, "ids[%d] = %d is out of range", k, ids[k]);
+                break;
+            }
+            if (seen[ids[k]]) {
+                s = fail(DR_E_INVALID, "ids[%d] = %d is repeated", k, ids[k]);
+                break;
+            }
             seen[ids[k]] = 1;
         }
+        for (int32_t j = 0; j < k; ++j) seen[ids[j]] = 0;
+        return s;
     }
     return DR_OK;
 }
@@ -832,9 +919,11 @@ dr_status check_start(int32_t start, bool allow_resume)
 }
 
 // Stages F (may be NULL), ids, starts (may be NULL) and the largest-first
-// slot order, and uploads them.
+// slot order, and uploads them.  order_slots = false leaves the identity
+// order (the launch loop does not use it) and allocates no host memory
+// (last_ids holds n_problems from creation on).
 dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
-                int32_t n_ids)
+                int32_t n_ids, bool order_slots = true)
 {
     HIPCHECK(hipEventSynchronize(b->staged)); // previous staging consumed
     if (F) std::memcpy(b->h_F, F, 9 * sizeof(double) * (size_t)n_ids);
@@ -846,11 +935,12 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
         if (starts) b->h_starts[k] = starts[k];
     }
     // slots grouped by size class, largest problem first within a class
-    std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
-        const int cs = b->class_of[b->h_ids[s]], ct = b->class_of[b->h_ids[t]];
-        if (cs != ct) return cs < ct;
-        return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
-    });
+    if (order_slots)
+        std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
+            const int cs = b->class_of[b->h_ids[s]], ct = b->class_of[b->h_ids[t]];
+            if (cs != ct) return cs < ct;
+            return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
+        });
     std::fill(b->slot_count.begin(), b->slot_count.end(), 0);
     for (int32_t k = 0; k < n_ids; ++k) ++b->slot_count[b->class_of[b->h_ids[k]]];
     for (size_t c = 0, off = 0; c < b->classes.size(); ++c) {
@@ -910,8 +1000,28 @@ dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sig
 
 // Launches the staged slots: one DR + stress launch per size class with
 // slots, concurrently on the class streams (fork / join on the batch stream).
-dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
+// With the tail hand-off, the problems still running once at most tail_at
+// of the launch remain leave their workgroups and a cooperative group launch
+// finishes them (tail = false: no hand-off, e.g. under graph capture).
+dr_status launch_or_fail(dr_batch *b, const SolveArgs &a_in, bool tail = true)
 {
+    SolveArgs a = a_in;
+    const bool hand_off = tail && b->tail_group > 0 && b->opt.tail_at > 0;
+    if (hand_off) {
+        a.tail_at = b->opt.tail_at;
+        int rc = drk::launch_fill_i32(b->d_live, a.n_solve, 1, b->stream);
+        if (rc == 0) rc = drk::launch_fill_i32(b->d_tail_count, 0, 1, b->stream);
+        if (rc != 0) return fail(DR_E_DEVICE, "tail counters: %s", drk::kernel_error_string(rc));
+    }
+    auto tail_launch = [&]() -> dr_status {
+        if (!hand_off) return DR_OK;
+        SolveArgs at = a;
+        at.tail_at = 0;
+        at.group = b->tail_group;
+        const int rc = drk::launch_tail(at, b->tail_plan, b->opt.tail_at, b->stream);
+        if (rc != 0) return fail(DR_E_DEVICE, "group launch failed: %s", drk::kernel_error_string(rc));
+        return DR_OK;
+    };
     int used = 0, only = -1;
     for (size_t c = 0; c < b->classes.size(); ++c)
         if (b->slot_count[c] > 0) { ++used; only = (int)c; }
@@ -923,7 +1033,10 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
         if (rc != 0) return fail(DR_E_DEVICE, "solve launch failed: %s", drk::kernel_error_string(rc));
         return DR_OK;
     };
-    if (used == 1) return one((size_t)only, b->stream);
+    if (used == 1) {
+        dr_status s = one((size_t)only, b->stream);
+        return s != DR_OK ? s : tail_launch();
+    }
     HIPCHECK(hipEventRecord(b->fork, b->stream));
     for (size_t c = 0; c < b->classes.size(); ++c) {
         if (b->slot_count[c] == 0) continue;
@@ -934,7 +1047,7 @@ dr_status launch_or_fail(dr_batch *b, const SolveArgs &a)
     }
     for (size_t c = 0; c < b->classes.size(); ++c)
         if (b->slot_count[c] > 0) HIPCHECK(hipStreamWaitEvent(b->stream, b->classes[c].done, 0));
-    return DR_OK;
+    return tail_launch();
 }
 
 } // namespace
@@ -1065,6 +1178,8 @@ dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_
     b->n_max = pk.n_max;
     b->desc = pk.desc;
     b->running.assign(b->P, 0);
+    b->seen.assign(b->P, 0);
+    b->last_ids.reserve(b->P);
     // running-state records: each problem at its node_base, or (a pool's
     // arena) placed when a solve is admitted
     b->state_nodes = arena_nodes > 0 ? arena_nodes : b->total_nodes;
@@ -1093,6 +1208,7 @@ dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_
     }
     s = create_device(b, pk);
     if (s == DR_OK) s = build_classes(b, {});
+    if (s == DR_OK && opt->tail_at > 0) s = plan_tail(b);
     if (s == DR_OK) {
         hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
         if (e != hipSuccess) s = fail(DR_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
@@ -1123,6 +1239,8 @@ void dr_options_default(dr_options *o)
     o->chunk = 0;
     o->stall_window = 0;
     o->energy_tol = 0.0;
+    o->tail_at = 0;
+    o->tail_group = 0;
 }
 
 const char *dr_last_error(void) { return g_err.c_str(); }
@@ -1358,25 +1476,28 @@ dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n
         if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;
         for (int32_t k = 0; k < n_ids; ++k)
             if ((s = check_F(F, k)) != DR_OK) return s;
-        if (scatter && !b->d_gscat)
+        double *gbuf = b->d_gscat, *partial = b->d_partial, *scalars = b->d_scalars;
+        if (scatter && !b->d_gscat) {
             HIPCHECK(hipMalloc(&b->d_gscat, sizeof(double) * 3 * (size_t)std::max(b->n_max, 1)));
-        if ((s = stage(b, F, ids, nullptr, n_ids)) != DR_OK) return s;
+            gbuf = b->d_gscat;
+        }
+        if ((s = stage(b, F, ids, nullptr, n_ids, false)) != DR_OK) return s;
         SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
         a.order = nullptr;
         hipStream_t st = b->stream;
         for (int32_t slot = 0; slot < n_ids; ++slot) {
             const ProbDesc &d = b->desc[b->h_ids[slot]];
-            int rc = drk::launch_loop_kernels(a, slot, 0, d.N, b->d_partial, b->d_scalars, 0, 0.0,
-                                              0.0, 0, b->d_gscat, st);
+            int rc = drk::launch_loop_kernels(a, slot, 0, d.N, partial, scalars, 0, 0.0,
+                                              0.0, 0, gbuf, st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop set-up launch failed: %s", drk::kernel_error_string(rc));
             int64_t n = 0;
             double rho = 0.0, ke = 0.0;
             int status = DR_MAX_ITER;
             for (;;) {
-                rc = drk::launch_loop_kernels(a, slot, scatter ? 3 : 1, d.N, b->d_partial,
-                                              b->d_scalars, n, 0.0, 0.0, 0, b->d_gscat, st);
+                rc = drk::launch_loop_kernels(a, slot, scatter ? 3 : 1, d.N, partial, scalars, n, 0.0,
+                                              0.0, 0, gbuf, st);
                 if (rc != 0) return fail(DR_E_DEVICE, "loop pass launch failed: %s", drk::kernel_error_string(rc));
-                HIPCHECK(hipMemcpyAsync(b->h_scalars, b->d_scalars, 3 * sizeof(double),
+                HIPCHECK(hipMemcpyAsync(b->h_scalars, scalars, 3 * sizeof(double),
                                         hipMemcpyDeviceToHost, st));
                 HIPCHECK(hipStreamSynchronize(st));
                 ++n;
@@ -1388,8 +1509,8 @@ dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n
                 if (rho <= b->opt.tol) { status = DR_CONVERGED; break; }
                 if (n >= b->opt.max_iter) { status = DR_MAX_ITER; break; }
             }
-            rc = drk::launch_loop_kernels(a, slot, 2, d.N, b->d_partial, b->d_scalars, n, rho, ke,
-                                          status, b->d_gscat, st);
+            rc = drk::launch_loop_kernels(a, slot, 2, d.N, partial, scalars, n, rho, ke, status, gbuf,
+                                          st);
             if (rc != 0) return fail(DR_E_DEVICE, "loop stress launch failed: %s", drk::kernel_error_string(rc));
             b->running[b->h_ids[slot]] = 0;
         }
@@ -1512,7 +1633,7 @@ dr_status dr_graph_capture(dr_batch *b, const double *F_device, const int32_t *i
         SolveArgs a = make_args(b, n_ids, start, b->opt.max_iter);
         a.F = F_device;
         HIPCHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        s = launch_or_fail(b, a);
+        s = launch_or_fail(b, a, false); // the cooperative group launch is not captured
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (s != DR_OK) { if (g) (void)hipGraphDestroy(g); return s; }

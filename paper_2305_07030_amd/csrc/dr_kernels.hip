@@ -24,15 +24,15 @@ struct UPos {
 
 constexpr int kStressBlock = 256;
 
-__global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
+// Both stress forms of problem p (one workgroup of kStressBlock threads).
+__device__ void stress_of(const SolveArgs &A, int p)
 {
     __shared__ double red[(kStressBlock / kWave) * kRedStride];
     constexpr int NW = kStressBlock / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
-    const int slot = A.order ? A.order[slot0 + (int)blockIdx.x] : slot0 + (int)blockIdx.x;
-    const int p = A.ids ? A.ids[slot] : slot;
     const int st = A.status[p];
-    if (st == kStatusRunning || st == kStatusIdle) return; // uniform over the workgroup
+    // nothing to do while a solve runs, before any solve, or after an abort
+    if (st == kStatusRunning || st == kStatusIdle || st == kStatusAborted) return; // uniform
     const ProbDesc P = A.probs[p];
     double F[9];
     for (int k = 0; k < 9; ++k) F[k] = A.F_cur[9 * (int64_t)p + k];
@@ -68,6 +68,20 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
         if (tid < 9) A.sigma[9 * (int64_t)p + tid] = t / J;
         else A.sigma_fib[9 * (int64_t)p + tid - 9] = t / J;
     }
+}
+
+// One workgroup per slot (slots slot0 + blockIdx of the launch order).
+__global__ void __launch_bounds__(kStressBlock) k_stress(SolveArgs A, int slot0)
+{
+    const int slot = A.order ? A.order[slot0 + (int)blockIdx.x] : slot0 + (int)blockIdx.x;
+    stress_of(A, A.ids ? A.ids[slot] : slot);
+}
+
+// One workgroup per entry of the tail list (the problems a group launch finished).
+__global__ void __launch_bounds__(kStressBlock) k_stress_tail(SolveArgs A)
+{
+    if ((int)blockIdx.x >= *A.tail_count) return;
+    stress_of(A, A.tail_list[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -368,6 +382,34 @@ int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, do
                            rho, ke, status);
         hipLaunchKernelGGL(k_stress, dim3(1), dim3(kStressBlock), 0, st, a, slot);
     }
+    return (int)hipGetLastError();
+}
+
+int group_grid_capacity(int fp32, int block, int lds_bytes, int *capacity)
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    int rc = fp32 ? group_capacity_p32(block, lds_bytes, &per_cu) : group_capacity_p64(block, lds_bytes, &per_cu);
+    if (rc != 0) return rc;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return (int)e;
+    *capacity = per_cu * cus;
+    return 0;
+}
+
+int launch_tail(const SolveArgs &a, const LaunchPlan &plan, int n_groups, void *stream)
+{
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (n_groups <= 0) return 0;
+    const int slots = 8 * ((n_groups + 7) / 8);
+    // fresh barrier counters and abort flags for the groups of this launch
+    int rc = launch_fill_i32(reinterpret_cast<int32_t *>(a.gbar), 0, slots, stream);
+    if (rc == 0) rc = launch_fill_i32(a.gabort, 0, slots, stream);
+    if (rc != 0) return rc;
+    const int grid = group_grid(n_groups, a.group);
+    rc = plan.fp32 ? launch_group_p32(a, plan, grid, st) : launch_group_p64(a, plan, grid, st);
+    if (rc != 0) return rc;
+    hipLaunchKernelGGL(k_stress_tail, dim3(n_groups), dim3(kStressBlock), 0, st, a);
     return (int)hipGetLastError();
 }
 

@@ -38,6 +38,12 @@ constexpr int kStatusRunning = 3;
 constexpr int kStatusIdle = 4;
 constexpr int kStatusStalled = 5;
 constexpr int kStatusEnergy = 6;
+constexpr int kStatusAborted = 7; // a group barrier's wait timed out
+
+// Workgroup groups: at most kGroupMax workgroups share one problem, at most
+// kTailMax problems go to one group launch.
+constexpr int kGroupMax = 16;
+constexpr int kTailMax = 256;
 
 // Slot start codes: a dr_start value starts a new solve; kResume continues
 // the problem's running solve from the state saved in HBM.
@@ -122,6 +128,18 @@ struct SolveArgs {
                               //   sum g.(w_old + w_new), sum m |w_old|^2, last g.w_new
     double *e_work;           // [P] work of the internal forces of the last / running solve
     double *e_damp;           // [P] work dissipated by damping
+    // tail hand-off: once at most tail_at problems of a launch still run,
+    // each leaves its workgroup (state saved) at its next check and joins the
+    // tail list; a group launch then finishes them with `group` workgroups each
+    int32_t tail_at;          // 0 = off
+    int32_t *live;            // [1] problems of the launch not finished (tail_at > 0)
+    int32_t *tail_list;       // [kTailMax] problems handed off
+    int32_t *tail_count;      // [1] entries of tail_list
+    int64_t *n_begin;         // [P] pass count at which a handed-off solve's launch began
+    int32_t group;            // workgroups per problem of a group launch
+    uint32_t *gbar;           // [kTailMax] barrier counters of the groups
+    int32_t *gabort;          // [kTailMax] abort flags of the groups
+    double *gpart;            // [kTailMax * 2 * kGroupMax * 4] partial sums of the groups
 };
 
 // Launch shape of one batched solve.
@@ -141,6 +159,18 @@ int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, do
                         double *out_scalars, int64_t n_done, double rho, double ke, int status,
                         double *gbuf, void *stream);
 int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream);
+// The group launch of the tail hand-off (cooperative: all its workgroups are
+// co-resident) for up to n_groups handed-off problems, then the stress of the
+// problems it finished; plan.block is the workgroup size (512 or 1024),
+// plan.lds_bytes its LDS, a.group the workgroups per problem.
+int launch_tail(const SolveArgs &a, const LaunchPlan &plan, int n_groups, void *stream);
+// Workgroups of the group kernel (fp32, block, lds_bytes) that the current
+// device holds at once.
+int group_grid_capacity(int fp32, int block, int lds_bytes, int *capacity);
+// Workgroups in a group launch for n_groups groups of G members: whole
+// rounds of 8 groups (one per XCD).
+inline int group_grid(int n_groups, int G) { return 8 * G * ((n_groups + 7) / 8); }
 const char *kernel_error_string(int code);
+
 
 } // namespace drk

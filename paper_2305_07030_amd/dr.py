@@ -16,6 +16,7 @@ from . import build as _build
 
 DR_OK, DR_E_INVALID, DR_E_NOMEM, DR_E_DEVICE, DR_E_STATE = 0, -1, -2, -3, -4
 DR_CONVERGED, DR_MAX_ITER, DR_NONFINITE, DR_RUNNING, DR_IDLE, DR_STALLED, DR_ENERGY = 0, 1, 2, 3, 4, 5, 6
+DR_ABORTED = 7
 DR_FP64, DR_FP32 = 0, 1
 DR_RESUME, DR_START_AFFINE, DR_START_ZERO, DR_START_WARM = -1, 0, 1, 2
 DR_PLACE_AUTO, DR_PLACE_LDS, DR_PLACE_GLOBAL = 0, 1, 2
@@ -60,7 +61,9 @@ class dr_options(C.Structure):
                 ("placement", C.c_int32),
                 ("chunk", C.c_int32),
                 ("stall_window", C.c_int64),
-                ("energy_tol", C.c_double)]
+                ("energy_tol", C.c_double),
+                ("tail_at", C.c_int32),
+                ("tail_group", C.c_int32)]
 
 
 _lib = None
@@ -427,7 +430,7 @@ class DRBatch:
 
     def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
                  block=0, placement=DR_PLACE_AUTO, chunk=0, stall_window=0, precision=DR_FP64,
-                 energy_tol=0.0, stream=None, workspace=None):
+                 energy_tol=0.0, tail_at=0, tail_group=0, stream=None, workspace=None):
         """workspace: None (the library allocates), or a device tensor whose
         storage holds the batch's device arrays (at least
         workspace_bytes(...) bytes, 256-byte aligned); it is kept referenced
@@ -437,7 +440,8 @@ class DRBatch:
         self.total_nodes = batch.total_nodes
         self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
                                 dt_safety=dt_safety, block=block, placement=placement,
-                                chunk=chunk, stall_window=stall_window, energy_tol=energy_tol)
+                                chunk=chunk, stall_window=stall_window, energy_tol=energy_tol,
+                                tail_at=tail_at, tail_group=tail_group)
         st = stream if stream is not None else current_stream()
         self.workspace = workspace
         if workspace is None:
