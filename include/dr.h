@@ -341,6 +341,23 @@ dr_status dr_solve_loop(dr_batch *b, const double *F, const int32_t *ids,
 dr_status dr_solve_loop_scatter(dr_batch *b, const double *F, const int32_t *ids,
                                 int32_t n_ids, int32_t start);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * dr_solve_loop_scatter, but its scratch (the force accumulators, the
+ * per-block partial sums and the reduced scalars) lives in one fixed device
+ * array of the library (6.3 MB, one per GPU, held until the process ends)
+ * instead of the batch's buffers, and the call allocates nothing.  Every
+ * problem in ids must have at most 262144 nodes (DR_E_INVALID otherwise).
+ * All calls on one GPU share that array: calls that overlap on one GPU (from
+ * several threads or batches) race, and must be serialised by the caller.
+ * The accumulators are cleared every pass, so nothing carries over from the
+ * previous call.  Same inputs, outputs and errors as dr_solve_loop_scatter
+ * otherwise (DR_E_DEVICE if the array's address cannot be looked up).
+ */
+dr_status dr_solve_loop_scatter_noalloc(dr_batch *b, const double *F, const int32_t *ids,
+                                        int32_t n_ids, int32_t start);
+
 /* Information about the packed batch and the launch chosen for it.
  *   n_problems, total_nodes, total_fibers, block (threads per workgroup),
  *   lds_bytes (dynamic LDS per workgroup), nodes_per_thread. Any may be NULL. */

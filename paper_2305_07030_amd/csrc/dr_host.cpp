@@ -1461,9 +1461,11 @@ namespace {
 
 // The per-problem launch loop: one problem after the other, a few kernels per
 // pass and the stop test on the host.  scatter: forces by the zero + atomic
-// scatter kernel instead of the deterministic gather.
+// scatter kernel instead of the deterministic gather.  noalloc: the scratch
+// (force accumulators, partial sums, scalars) comes from the library's fixed
+// per-device array instead of the batch's buffers, and nothing is allocated.
 dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n_ids,
-                     int32_t start, bool scatter)
+                     int32_t start, bool scatter, bool noalloc = false)
 {
     try {
         g_err.clear();
@@ -1477,7 +1479,22 @@ dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n
         for (int32_t k = 0; k < n_ids; ++k)
             if ((s = check_F(F, k)) != DR_OK) return s;
         double *gbuf = b->d_gscat, *partial = b->d_partial, *scalars = b->d_scalars;
-        if (scatter && !b->d_gscat) {
+        if (noalloc) {
+            for (int32_t k = 0; k < n_ids; ++k) {
+                const int32_t p = ids ? ids[k] : k;
+                if (b->hp[p].N > drk::kNoAllocMaxNodes)
+                    return fail(DR_E_INVALID, "problem %d has %d nodes; the allocation-free loop takes "
+                                "at most %d", p, b->hp[p].N, drk::kNoAllocMaxNodes);
+            }
+            HIPCHECK(hipSetDevice(b->device));
+            void *base = nullptr;
+            const int rc = drk::noalloc_scratch(&base);
+            if (rc != 0) return fail(DR_E_DEVICE, "scratch address: %s", drk::kernel_error_string(rc));
+            char *c = static_cast<char *>(base);
+            gbuf = reinterpret_cast<double *>(c + drk::kNoAllocForceOff);
+            partial = reinterpret_cast<double *>(c + drk::kNoAllocPartialOff);
+            scalars = reinterpret_cast<double *>(c + drk::kNoAllocScalarOff);
+        } else if (scatter && !b->d_gscat) {
             HIPCHECK(hipMalloc(&b->d_gscat, sizeof(double) * 3 * (size_t)std::max(b->n_max, 1)));
             gbuf = b->d_gscat;
         }
@@ -1536,6 +1553,12 @@ dr_status dr_solve_loop_scatter(dr_batch *b, const double *F, const int32_t *ids
                                 int32_t start)
 {
     return solve_loop(b, F, ids, n_ids, start, true);
+}
+
+dr_status dr_solve_loop_scatter_noalloc(dr_batch *b, const double *F, const int32_t *ids,
+                                        int32_t n_ids, int32_t start)
+{
+    return solve_loop(b, F, ids, n_ids, start, true, true);
 }
 
 dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_nodes,

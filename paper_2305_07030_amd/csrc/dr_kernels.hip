@@ -1,6 +1,8 @@
 // HIP kernels of libdr that are not templates (stress average, the
 // launch-loop comparator, fills) and the launch dispatch.  The persistent
 // DR kernels are instantiated in dr_k_reg_*.hip and dr_k_glb_*.hip.
+#include <mutex>
+
 #include "dr_device.h"
 
 namespace drk {
@@ -420,6 +422,39 @@ int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream)
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, n);
     return (int)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free launch loop: one array per device, held by
+// the library until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and is kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+} // namespace
+
+int noalloc_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *ptr = g_scratch_addr[dev];
+    return 0;
 }
 
 const char *kernel_error_string(int code)

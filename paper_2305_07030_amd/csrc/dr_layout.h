@@ -172,5 +172,19 @@ int group_grid_capacity(int fp32, int block, int lds_bytes, int *capacity);
 inline int group_grid(int n_groups, int G) { return 8 * G * ((n_groups + 7) / 8); }
 const char *kernel_error_string(int code);
 
+// Allocation-free launch loop: the scratch of one problem's solve (force
+// accumulators of the atomic scatter, per-block partial sums, the reduced
+// scalars) in a fixed device array of the library, for problems of at most
+// kNoAllocMaxNodes nodes.  Byte offsets within it:
+constexpr int kNoAllocMaxNodes = 262144;
+constexpr size_t kNoAllocForceOff = 0;
+constexpr size_t kNoAllocPartialOff = 3 * sizeof(double) * (size_t)kNoAllocMaxNodes;
+constexpr size_t kNoAllocScalarOff =
+    kNoAllocPartialOff + ((3 * sizeof(double) * (size_t)(kNoAllocMaxNodes / 256 + 2) + 255) / 256) * 256;
+constexpr size_t kNoAllocScratchBytes = kNoAllocScalarOff + 256;
+// Device address of that array on the current device (looked up once per
+// device); 0 or a hipError_t.
+int noalloc_scratch(void **ptr);
+
 
 } // namespace drk

@@ -28,7 +28,7 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_batch_workspace_bytes",
            "dr_batch_create_in", "dr_solve", "dr_solve_device",
            "dr_stress", "dr_advance", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
-           "dr_solve_loop_scatter", "dr_batch_info",
+           "dr_solve_loop_scatter", "dr_solve_loop_scatter_noalloc", "dr_batch_info",
            "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
            "dr_graph_launch", "dr_batch_destroy", "dr_pool_create", "dr_pool_submit", "dr_pool_poll",
            "dr_pool_status", "dr_pool_destroy", "dr_state_bytes_per_node", "dr_last_error")
@@ -130,6 +130,8 @@ def load():
     lib.dr_solve_loop.restype = C.c_int
     lib.dr_solve_loop_scatter.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
     lib.dr_solve_loop_scatter.restype = C.c_int
+    lib.dr_solve_loop_scatter_noalloc.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    lib.dr_solve_loop_scatter_noalloc.restype = C.c_int
     lib.dr_batch_info.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.dr_batch_info.restype = C.c_int
     lib.dr_batch_scalars.argtypes = [vp, vp, vp, vp]
@@ -279,6 +281,13 @@ def dr_solve_loop_scatter(h: int, F: np.ndarray, ids: Optional[np.ndarray] = Non
     F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
     idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
     _check(load().dr_solve_loop_scatter(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
+
+
+def dr_solve_loop_scatter_noalloc(h: int, F: np.ndarray, ids: Optional[np.ndarray] = None,
+                                  start: int = DR_START_AFFINE):
+    F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
+    idsa = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    _check(load().dr_solve_loop_scatter_noalloc(h, _ptr(F), _ptr(idsa), F.shape[0], int(start)))
 
 
 def dr_stress(h: int, n_ids: int, total_nodes: Optional[int] = None, want_u: bool = False) -> dict:
