@@ -42,6 +42,17 @@
  *      r_b = -g_b, J = det F, V0 = 1, c0 = (1/2, 1/2, 1/2), row-major with
  *      sigma_ij = sum r_i y_j.  The fiber form
  *      sigma_fib = 1/(J V0) sum_f T_f d_f (x) d_f / l_f is returned beside it.
+ *   R16 "compute next time step" taken literally (optional, dt_rule = 1): at
+ *      the top of each pass the pass's step is computed from the current
+ *      state, dt = min(dt0, s * 2 / w(u)), with dt0 the constant step of R3
+ *      and w(u)^2 = max over free nodes i of (2 / m_i) sum_{f at i} k_f(u),
+ *      k_f = EA l / L^2, the fiber's axial tangent stiffness at its current
+ *      length.  (Its transverse, geometric stiffness T / l is smaller in
+ *      tension and negative in compression, where it drives buckling, a
+ *      growth that no step size removes, so it does not bound the step.)
+ *      Both half velocity updates of the pass use the step.
+ *      Where the current stiffness stays within R3's headroom every step is
+ *      dt0 and the iteration is the constant-step one exactly.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so the
  * rounding follows the source order).
@@ -118,6 +129,34 @@ double oracle_energy(int N, const double *X, const double *u, int M,
         W += EA[f] * L[f] * (lam * lam * lam - 3.0 * lam + 2.0) / 6.0;
     }
     return W;
+}
+
+/* Step of R16 at displacement u: min(dt0, s 2 / w(u)) (dt0 when no free
+ * node carries stiffness). */
+static double step_at(int N, const double *X, const double *u, int M, const int *fib,
+                      const double *EA, const double *L, const unsigned char *fixed,
+                      const double *m, double dt0, double dt_safety, double *ksum)
+{
+    for (int i = 0; i < N; ++i) ksum[i] = 0.0;
+    for (int f = 0; f < M; ++f) {
+        int a = fib[2 * f], b = fib[2 * f + 1];
+        double d[3];
+        for (int k = 0; k < 3; ++k)
+            d[k] = (X[3 * b + k] + u[3 * b + k]) - (X[3 * a + k] + u[3 * a + k]);
+        double l = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double kf = EA[f] * l / (L[f] * L[f]);
+        ksum[a] += kf;
+        ksum[b] += kf;
+    }
+    double w2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+        if (fixed[i]) continue;
+        double wi = 2.0 / m[i] * ksum[i];
+        if (wi > w2) w2 = wi;
+    }
+    if (!(w2 > 0.0)) return dt0;
+    double dt = dt_safety * 2.0 / sqrt(w2);
+    return dt < dt0 ? dt : dt0;
 }
 
 static double det3(const double *F)
@@ -215,7 +254,9 @@ static void stress(int N, const double *X, const double *u, int M, const int *fi
  * Outputs: u[3N], sigma[9], sigma_fib[9], iteration count, final residual,
  * kinetic energy, and the dt / c that were used.  Optional trace: when
  * rho_trace is not NULL, the residual of pass n is stored at rho_trace[n-1]
- * for n <= trace_len.
+ * for n <= trace_len.  dt_rule: 0 = the constant step of R3, 1 = the
+ * per-pass step of R16.  work_out (optional): the internal and damping work,
+ * then the smallest step used.
  * Returns OR_CONVERGED / OR_MAX_ITER / OR_NONFINITE, or a negative error.
  */
 int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA,
@@ -224,7 +265,7 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
                  double tol, long max_iter, double beta, double dt_safety,
                  double *u, double *sigma, double *sigma_fib, long *iters,
                  double *rho_out, double *ke_out, double *dt_out, double *c_out,
-                 double *rho_trace, long trace_len, double *work_out)
+                 double *rho_trace, long trace_len, double *work_out, int dt_rule)
 {
     if (N < 1 || M < 0 || max_iter < 1) return OR_EINVAL;
     size_t n3 = 3 * (size_t)N;
@@ -234,16 +275,18 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
     double *a = (double *)calloc(n3, sizeof(double));
     double *g = (double *)calloc(n3, sizeof(double));
     double *g_prev = (double *)calloc(n3, sizeof(double));
-    if (!L || !m || !v || !a || !g || !g_prev) {
-        free(L); free(m); free(v); free(a); free(g); free(g_prev);
+    double *ksum = (double *)calloc((size_t)N, sizeof(double));
+    if (!L || !m || !v || !a || !g || !g_prev || !ksum) {
+        free(L); free(m); free(v); free(a); free(g); free(g_prev); free(ksum);
         return OR_ENOMEM;
     }
-    double dt, c, s_floor;
-    int rc = oracle_derived(N, X, M, fib, EA, fixed, beta, dt_safety, L, m, &dt, &c, &s_floor);
+    double dt0, c, s_floor;
+    int rc = oracle_derived(N, X, M, fib, EA, fixed, beta, dt_safety, L, m, &dt0, &c, &s_floor);
     if (rc != 0) {
-        free(L); free(m); free(v); free(a); free(g); free(g_prev);
+        free(L); free(m); free(v); free(a); free(g); free(g_prev); free(ksum);
         return rc;
     }
+    double dt = dt0, dt_min = dt0;
 
     /* Set displacement boundary conditions and the start state (R5). */
     for (int i = 0; i < N; ++i) {
@@ -282,7 +325,12 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
     double work_int = 0.0, work_damp = 0.0;
     int status = OR_MAX_ITER;
     do {
-        /* compute next time step (constant, R3) */
+        /* compute next time step: constant (R3), or from the current
+         * state (R16) */
+        if (dt_rule) {
+            dt = step_at(N, X, u, M, fib, EA, L, fixed, m, dt0, dt_safety, ksum);
+            if (dt < dt_min) dt_min = dt;
+        }
         /* partial velocity update (free dof) */
         for (int i = 0; i < N; ++i) {
             if (fixed[i]) continue;
@@ -348,13 +396,14 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
     *iters = n;
     *rho_out = rho;
     *ke_out = ke;
-    *dt_out = dt;
+    *dt_out = dt0;
     *c_out = c;
     if (work_out) {
         work_out[0] = work_int;
         work_out[1] = work_damp;
+        work_out[2] = dt_min;
     }
     (void)t;
-    free(L); free(m); free(v); free(a); free(g); free(g_prev);
+    free(L); free(m); free(v); free(a); free(g); free(g_prev); free(ksum);
     return status;
 }

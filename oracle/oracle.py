@@ -53,7 +53,7 @@ def _load():
             C.c_double, C.c_long, C.c_double, C.c_double,
             _dp, _dp, _dp, C.POINTER(C.c_long),
             C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-            C.c_void_p, C.c_long, _dp]
+            C.c_void_p, C.c_long, _dp, C.c_int]
         lib.oracle_internal_force.restype = None
         lib.oracle_internal_force.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip, _dp, _dp, _dp]
         lib.oracle_energy.restype = C.c_double
@@ -84,6 +84,7 @@ class OracleResult:
     rho_trace: Optional[np.ndarray] = None
     work_int: float = 0.0   # work of the internal forces over the solve (trapezoid per pass)
     work_damp: float = 0.0  # work dissipated by the damping force
+    dt_min: float = 0.0     # smallest step used (the constant step unless dt_rule = 1)
 
 
 def derived(net, beta: float, dt_safety: float):
@@ -121,8 +122,10 @@ def energy(net, u: np.ndarray) -> float:
 
 
 def solve(net, F, *, tol=1e-8, max_iter=2_000_000, beta, dt_safety,
-          start=START_AFFINE, F_prev=None, u_prev=None, trace_len: int = 0) -> OracleResult:
-    """One DR solve of ``net`` under deformation gradient ``F`` (3x3)."""
+          start=START_AFFINE, F_prev=None, u_prev=None, trace_len: int = 0,
+          dt_rule: int = 0) -> OracleResult:
+    """One DR solve of ``net`` under deformation gradient ``F`` (3x3).
+    dt_rule 0: constant step (reading R3); 1: per-pass step (reading R16)."""
     lib = _load()
     N, M = net.n_nodes, net.n_fibers
     X = _c(net.X, np.float64).ravel()
@@ -139,17 +142,18 @@ def solve(net, F, *, tol=1e-8, max_iter=2_000_000, beta, dt_safety,
     u = np.zeros(3 * N); sig = np.zeros(9); sigf = np.zeros(9)
     it = C.c_long(); rho = C.c_double(); ke = C.c_double(); dt = C.c_double(); c = C.c_double()
     tr = np.zeros(max(trace_len, 1)) if trace_len > 0 else None
-    work = np.zeros(2)
+    work = np.zeros(3)
     rc = lib.oracle_solve(N, X, M, fib, EA, fixed, Fa, int(start), Fp, up,
                           float(tol), int(max_iter), float(beta), float(dt_safety),
                           u, sig, sigf, C.byref(it), C.byref(rho), C.byref(ke), C.byref(dt), C.byref(c),
-                          tr.ctypes.data if tr is not None else None, int(trace_len), work)
+                          tr.ctypes.data if tr is not None else None, int(trace_len), work,
+                          int(dt_rule))
     if rc < 0:
         raise ValueError("oracle_solve: invalid input (%d)" % rc)
     return OracleResult(rc, u.reshape(N, 3), sig.reshape(3, 3), sigf.reshape(3, 3), it.value,
                         rho.value, ke.value, dt.value, c.value,
                         tr[:min(it.value, trace_len)] if tr is not None else None,
-                        float(work[0]), float(work[1]))
+                        float(work[0]), float(work[1]), float(work[2]))
 
 
 def solve_batch(batch, *, threads: Optional[int] = None, **kw):

@@ -418,3 +418,62 @@ def test_energy_balance_terms(oracle_lib):
             bal = r.ke - r.work_int + r.work_damp
             assert abs(bal) <= bal_tol * max(r.ke, abs(r.work_int), r.work_damp), (K, bal)
             assert r.work_damp > 0.0
+
+
+# --------------------------------------------------------------------------
+# Fig. 1, "compute next time step" taken literally (reading R16): the step of
+# each pass from the current axial tangent stiffness, capped by the constant
+# step of R3.
+# --------------------------------------------------------------------------
+def test_step_rule_closed_form(oracle_lib):
+    """One pass from a stretched chain: the step the rule takes equals
+    min(dt0, s 2 / w) with w^2 = (2 / m_B)(EA1 l1 / L1^2 + EA2 l2 / L2^2),
+    the Gershgorin bound of the middle node at the start state (only the free
+    node counts)."""
+    O = oracle_lib
+    net = _chain()
+    F = np.diag([1.8, 1.0, 1.0])
+    u0 = np.vstack([F @ x - x for x in net.X])
+    u0[1] = [0.12, 0.01, -0.02]  # middle node off the affine position
+    r = O.solve(net, F, tol=1e-300, max_iter=1, beta=BETA, dt_safety=S, start=O.START_WARM,
+                F_prev=F, u_prev=u0, dt_rule=1)
+    x = net.X + u0
+    L1, L2 = 0.25, 0.35
+    l1 = np.linalg.norm(x[1] - x[0]); l2 = np.linalg.norm(x[2] - x[1])
+    mB = 0.5 * (L1 + L2)
+    w2 = 2.0 / mB * (net.EA[0] * l1 / L1 ** 2 + net.EA[1] * l2 / L2 ** 2)
+    expect = min(r.dt, S * 2.0 / math.sqrt(w2))
+    assert expect < r.dt  # the rule is active here
+    assert r.dt_min == pytest.approx(expect, rel=1e-14)
+    # dt0 of R3 is the same bound with the reference stiffness 1.1 EA / L
+    w02 = 2.0 / mB * 1.1 * (net.EA[0] / L1 + net.EA[1] / L2)
+    assert r.dt == pytest.approx(S * 2.0 / math.sqrt(w02), rel=1e-14)
+
+
+def test_step_rule_rescues_a_stretched_start(oracle_lib):
+    """The chain stretched four-fold from u = 0: the constant step is too long
+    for the stretched fibers' stiffness and the iteration diverges; with the
+    per-pass step it converges to the bisection equilibrium."""
+    O = oracle_lib
+    net = _chain()
+    F = np.diag([4.0, 1.0, 1.0])
+    a = O.solve(net, F, tol=1e-12, beta=0.05, dt_safety=S, start=O.START_ZERO)
+    b = O.solve(net, F, tol=1e-12, beta=0.05, dt_safety=S, start=O.START_ZERO, dt_rule=1)
+    assert a.status == O.NONFINITE
+    assert b.status == O.CONVERGED and b.dt_min < 0.5 * b.dt
+    xB, T, ell, e = _chain_equilibrium(net, F)
+    assert np.allclose(net.X[1] + b.u[1], xB, rtol=0, atol=1e-11)
+
+
+def test_step_rule_keeps_the_constant_step(oracle_lib):
+    """Where every fiber's stiffness stays within the 10 % headroom of R3 the
+    rule's step is dt0 on every pass and the solve is the constant-step one
+    bit for bit."""
+    O = oracle_lib
+    for batch in (I.config_single(), I.small_batch(3, 80, 300, 0.02, seed=5)):
+        for net, F in zip(batch.nets, batch.F):
+            a = O.solve(net, F, tol=1e-8, beta=BETA, dt_safety=S)
+            b = O.solve(net, F, tol=1e-8, beta=BETA, dt_safety=S, dt_rule=1)
+            assert b.dt_min == a.dt == b.dt
+            assert a.iters == b.iters and a.status == b.status
+            assert np.array_equal(a.u, b.u) and np.array_equal(a.sigma, b.sigma)
