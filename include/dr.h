@@ -172,6 +172,18 @@ typedef struct {
  *               let tail_at problems be resident at once), else 2..16;
  *               DR_E_INVALID at creation when tail_at x tail_group workgroups
  *               cannot be resident at once.
+ *   dt_rule     0 = one constant step per solve (reading R3 of Fig. 1's
+ *               "compute next time step"); 1 = a step per pass from the
+ *               current state (reading R16): dt_n = min(dt_{n-1},
+ *               dt_safety * 2 / w), w^2 = max over free nodes i of
+ *               (2 / m_i) sum_{f at i} EA_f l_f / L_f^2 (axial tangent
+ *               stiffness at the current length), from dt_0 = the constant
+ *               step; the step never grows back.  Identical results wherever
+ *               the step stays dt0; a fiber stretched beyond the constant
+ *               step's headroom no longer makes the iteration diverge.  Runs
+ *               its own kernel (global placement, 24 B more per node of
+ *               device memory); FP64 only, and not with energy_tol, tail_at
+ *               or the launch-loop comparator (DR_E_INVALID).
  */
 typedef struct {
     int32_t precision;
@@ -186,11 +198,12 @@ typedef struct {
     double energy_tol;
     int32_t tail_at;
     int32_t tail_group;
+    int32_t dt_rule;
 } dr_options;
 
 /* Fills *opt with the defaults: FP64, tol 1e-8, max_iter 2000000,
  * damping 1e-3, dt_safety 0.9, block 0, placement DR_PLACE_AUTO, chunk 0,
- * stall_window 0, energy_tol 0, tail_at 0, tail_group 0. */
+ * stall_window 0, energy_tol 0, tail_at 0, tail_group 0, dt_rule 0. */
 void dr_options_default(dr_options *opt);
 
 /*

@@ -115,6 +115,7 @@ struct dr_batch {
     uint32_t *d_gbar = nullptr;
     int64_t *d_n_begin = nullptr;
     double *d_gpart = nullptr;
+    double *d_abuf = nullptr, *d_dt_next = nullptr; // per-pass time step (dt_rule = 1)
     int32_t tail_group = 0;     // workgroups per handed-off problem (0: hand-off off)
     LaunchPlan tail_plan{};     // launch shape of the group kernel
     // caller-owned device workspace (dr_batch_create_in): every device array
@@ -171,7 +172,8 @@ void free_all(dr_batch *b)
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
                    b->d_e_work, b->d_e_damp, b->d_state_off, b->d_live, b->d_tail_list,
-                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart};
+                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart,
+                   b->d_abuf, b->d_dt_next};
     if (!b->ws)
         for (void *p : dev)
             if (p) (void)hipFree(p);
@@ -228,6 +230,13 @@ dr_status validate_options(const dr_options *o)
         return fail(DR_E_INVALID, "tail_at must be in [0, %d] (got %d)", drk::kTailMax, o->tail_at);
     if (o->tail_group != 0 && (o->tail_group < 2 || o->tail_group > drk::kGroupMax))
         return fail(DR_E_INVALID, "tail_group must be 0 or in [2, %d] (got %d)", drk::kGroupMax, o->tail_group);
+    if (o->dt_rule != 0 && o->dt_rule != 1)
+        return fail(DR_E_INVALID, "dt_rule must be 0 or 1 (got %d)", o->dt_rule);
+    if (o->dt_rule == 1) {
+        if (o->precision != DR_FP64) return fail(DR_E_INVALID, "dt_rule 1 is FP64 only");
+        if (o->energy_tol != 0.0) return fail(DR_E_INVALID, "dt_rule 1 does not track the energy balance");
+        if (o->tail_at != 0) return fail(DR_E_INVALID, "dt_rule 1 has no tail hand-off");
+    }
     return DR_OK;
 }
 
@@ -573,6 +582,10 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_e_work, P)
     ZS(d_e_damp, P)
     if (b->opt.energy_tol > 0.0) ZS(d_enode, 4 * nodes)
+    if (b->opt.dt_rule == 1) {
+        ZS(d_abuf, 3 * rec)
+        ZS(d_dt_next, P)
+    }
     ZS(d_live, 1)
     ZS(d_tail_count, 1)
     ZS(d_tail_list, drk::kTailMax)
@@ -869,6 +882,10 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.enode = b->d_enode;
     a.e_work = b->d_e_work;
     a.e_damp = b->d_e_damp;
+    a.dt_rule = b->opt.dt_rule;
+    a.dt_safety = b->opt.dt_safety;
+    a.abuf = b->d_abuf;
+    a.dt_next = b->d_dt_next;
     return a;
 }
 
@@ -1241,6 +1258,7 @@ void dr_options_default(dr_options *o)
     o->energy_tol = 0.0;
     o->tail_at = 0;
     o->tail_group = 0;
+    o->dt_rule = 0;
 }
 
 const char *dr_last_error(void) { return g_err.c_str(); }
@@ -1473,6 +1491,8 @@ dr_status solve_loop(dr_batch *b, const double *F, const int32_t *ids, int32_t n
         if (!F) return fail(DR_E_INVALID, "F is NULL");
         if (b->opt.precision != DR_FP64)
             return fail(DR_E_INVALID, "the launch-loop comparator is FP64 only");
+        if (b->opt.dt_rule != 0)
+            return fail(DR_E_INVALID, "the launch-loop comparator runs the constant step only");
         dr_status s = check_start(start, false);
         if (s != DR_OK) return s;
         if ((s = check_ids(b, ids, n_ids)) != DR_OK) return s;

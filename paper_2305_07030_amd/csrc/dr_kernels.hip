@@ -349,7 +349,7 @@ int launch_solve(const SolveArgs &a, const LaunchPlan &plan, void *stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (a.n_solve <= 0) return 0;
-    const int rc = launch_dr(a, plan, st);
+    const int rc = a.dt_rule ? launch_dtp(a, plan.block, stream) : launch_dr(a, plan, st);
     if (rc != 0) return rc;
     hipLaunchKernelGGL(k_stress, dim3(a.n_solve), dim3(kStressBlock), 0, st, a, 0);
     return (int)hipGetLastError();

@@ -140,6 +140,12 @@ struct SolveArgs {
     uint32_t *gbar;           // [kTailMax] barrier counters of the groups
     int32_t *gabort;          // [kTailMax] abort flags of the groups
     double *gpart;            // [kTailMax * 2 * kGroupMax * 4] partial sums of the groups
+    // per-pass time step (dt_rule = 1): the step's safety factor, the
+    // acceleration records and the step of each running solve's next pass
+    int32_t dt_rule;          // 0 = constant step, 1 = per-pass step (k_dr_dtp)
+    double dt_safety;
+    double *abuf;             // [records * 3] accelerations (dt_rule = 1)
+    double *dt_next;          // [P] step of the next pass of a running solve (dt_rule = 1)
 };
 
 // Launch shape of one batched solve.
@@ -159,6 +165,9 @@ int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, do
                         double *out_scalars, int64_t n_done, double rho, double ke, int status,
                         double *gbuf, void *stream);
 int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream);
+// The per-pass time-step kernel (global placement, FP64) with `block`
+// threads per workgroup (256, 512 or 1024).
+int launch_dtp(const SolveArgs &a, int block, void *stream);
 // The group launch of the tail hand-off (cooperative: all its workgroups are
 // co-resident) for up to n_groups handed-off problems, then the stress of the
 // problems it finished; plan.block is the workgroup size (512 or 1024),

@@ -63,7 +63,8 @@ class dr_options(C.Structure):
                 ("stall_window", C.c_int64),
                 ("energy_tol", C.c_double),
                 ("tail_at", C.c_int32),
-                ("tail_group", C.c_int32)]
+                ("tail_group", C.c_int32),
+                ("dt_rule", C.c_int32)]
 
 
 _lib = None
@@ -439,7 +440,7 @@ class DRBatch:
 
     def __init__(self, batch, *, tol=1e-8, max_iter=2_000_000, damping=1e-3, dt_safety=0.9,
                  block=0, placement=DR_PLACE_AUTO, chunk=0, stall_window=0, precision=DR_FP64,
-                 energy_tol=0.0, tail_at=0, tail_group=0, stream=None, workspace=None):
+                 energy_tol=0.0, tail_at=0, tail_group=0, dt_rule=0, stream=None, workspace=None):
         """workspace: None (the library allocates), or a device tensor whose
         storage holds the batch's device arrays (at least
         workspace_bytes(...) bytes, 256-byte aligned); it is kept referenced
@@ -450,7 +451,7 @@ class DRBatch:
         self.opt = make_options(precision=precision, tol=tol, max_iter=max_iter, damping=damping,
                                 dt_safety=dt_safety, block=block, placement=placement,
                                 chunk=chunk, stall_window=stall_window, energy_tol=energy_tol,
-                                tail_at=tail_at, tail_group=tail_group)
+                                tail_at=tail_at, tail_group=tail_group, dt_rule=dt_rule)
         st = stream if stream is not None else current_stream()
         self.workspace = workspace
         if workspace is None:
