@@ -5,5 +5,5 @@ this package.  It shares no code with the HIP path.
 """
 from .oracle import (  # noqa: F401
     CONVERGED, MAX_ITER, NONFINITE, START_AFFINE, START_ZERO, START_WARM,
-    OracleResult, build, derived, energy, internal_force, solve, solve_batch,
+    OracleResult, build, derived, energy, evaluate, internal_force, solve, solve_batch,
 )

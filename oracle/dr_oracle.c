@@ -44,13 +44,17 @@
  *      sigma_fib = 1/(J V0) sum_f T_f d_f (x) d_f / l_f is returned beside it.
  *   R16 "compute next time step" taken literally (optional, dt_rule = 1): at
  *      the top of each pass the pass's step is computed from the current
- *      state, dt = min(dt0, s * 2 / w(u)), with dt0 the constant step of R3
- *      and w(u)^2 = max over free nodes i of (2 / m_i) sum_{f at i} k_f(u),
+ *      state, dt_n = min(dt_{n-1}, s * 2 / w(u)), starting from dt_0 = the
+ *      constant step of R3, with w(u)^2 = max over free nodes i of
+ *      (2 / m_i) sum_{f at i} k_f(u),
  *      k_f = EA l / L^2, the fiber's axial tangent stiffness at its current
  *      length.  (Its transverse, geometric stiffness T / l is smaller in
  *      tension and negative in compression, where it drives buckling, a
  *      growth that no step size removes, so it does not bound the step.)
- *      Both half velocity updates of the pass use the step.
+ *      Both half velocity updates of the pass use the step.  The step never
+ *      grows back: a step that follows the stiffness up and down from pass to
+ *      pass pumps energy into a violent transient (a parametric excitation)
+ *      and made solves diverge that converge with the constant step.
  *      Where the current stiffness stays within R3's headroom every step is
  *      dt0 and the iteration is the constant-step one exactly.
  *
@@ -132,7 +136,7 @@ double oracle_energy(int N, const double *X, const double *u, int M,
 }
 
 /* Step of R16 at displacement u: min(dt0, s 2 / w(u)) (dt0 when no free
- * node carries stiffness). */
+ * node carries stiffness), dt0 the previous pass's step. */
 static double step_at(int N, const double *X, const double *u, int M, const int *fib,
                       const double *EA, const double *L, const unsigned char *fixed,
                       const double *m, double dt0, double dt_safety, double *ksum)
@@ -245,6 +249,43 @@ static void stress(int N, const double *X, const double *u, int M, const int *fi
 }
 
 /*
+ * The residual and the stress of a given state (R6, R7): rho of the
+ * displacement u[3N] (prescribed nodes included as given) and both stress
+ * forms under F.  Returns 0, or a negative error.  This evaluates the
+ * definitions the solve stops on and returns; it does not iterate.
+ */
+int oracle_evaluate(int N, const double *X, const double *u, int M, const int *fib,
+                    const double *EA, const unsigned char *fixed, const double *F,
+                    double *rho_out, double *sigma, double *sigma_fib)
+{
+    if (N < 1 || M < 0) return OR_EINVAL;
+    double *L = (double *)malloc(((size_t)M > 0 ? (size_t)M : 1) * sizeof(double));
+    double *m = (double *)malloc((size_t)N * sizeof(double));
+    double *g = (double *)calloc(3 * (size_t)N, sizeof(double));
+    if (!L || !m || !g) {
+        free(L); free(m); free(g);
+        return OR_ENOMEM;
+    }
+    double dt, c, s_floor;
+    int rc = oracle_derived(N, X, M, fib, EA, fixed, 0.0, 1.0, L, m, &dt, &c, &s_floor);
+    if (rc == 0) {
+        oracle_internal_force(N, X, u, M, fib, EA, L, g);
+        double gf2 = 0.0, gb2 = 0.0;
+        for (int i = 0; i < N; ++i)
+            for (int k = 0; k < 3; ++k) {
+                double gk = g[3 * i + k];
+                if (fixed[i]) gb2 += gk * gk; else gf2 += gk * gk;
+            }
+        double den = sqrt(gb2);
+        if (den < s_floor) den = s_floor;
+        *rho_out = sqrt(gf2) / den;
+        stress(N, X, u, M, fib, EA, L, fixed, g, F, sigma, sigma_fib);
+    }
+    free(L); free(m); free(g);
+    return rc;
+}
+
+/*
  * One dynamic-relaxation solve (Fig. 1).
  *
  * Inputs: N nodes with reference coordinates X[3N] (xyz interleaved), M
@@ -328,7 +369,7 @@ int oracle_solve(int N, const double *X, int M, const int *fib, const double *EA
         /* compute next time step: constant (R3), or from the current
          * state (R16) */
         if (dt_rule) {
-            dt = step_at(N, X, u, M, fib, EA, L, fixed, m, dt0, dt_safety, ksum);
+            dt = step_at(N, X, u, M, fib, EA, L, fixed, m, dt, dt_safety, ksum);
             if (dt < dt_min) dt_min = dt;
         }
         /* partial velocity update (free dof) */

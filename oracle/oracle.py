@@ -56,6 +56,9 @@ def _load():
             C.c_void_p, C.c_long, _dp, C.c_int]
         lib.oracle_internal_force.restype = None
         lib.oracle_internal_force.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip, _dp, _dp, _dp]
+        lib.oracle_evaluate.restype = C.c_int
+        lib.oracle_evaluate.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip, _dp, _bp, _dp,
+                                        C.POINTER(C.c_double), _dp, _dp]
         lib.oracle_energy.restype = C.c_double
         lib.oracle_energy.argtypes = [C.c_int, _dp, _dp, C.c_int, _ip, _dp, _dp]
         lib.oracle_derived.restype = C.c_int
@@ -119,6 +122,23 @@ def energy(net, u: np.ndarray) -> float:
     L = np.linalg.norm(net.X[net.fibers[:, 1]] - net.X[net.fibers[:, 0]], axis=1)
     return lib.oracle_energy(N, _c(net.X, np.float64).ravel(), _c(u, np.float64).ravel(), M,
                              _c(net.fibers, np.int32).ravel(), _c(net.EA, np.float64), _c(L, np.float64))
+
+
+def evaluate(net, F, u: np.ndarray):
+    """Residual rho (reading R6) and both stress forms (R7) of the state u
+    (N x 3 displacements, prescribed nodes as given) under F, without
+    iterating: whether a state returned by another solver is an equilibrium,
+    and what its stress is, by this file's definitions."""
+    lib = _load()
+    N, M = net.n_nodes, net.n_fibers
+    rho = C.c_double()
+    sig = np.zeros(9); sigf = np.zeros(9)
+    rc = lib.oracle_evaluate(N, _c(net.X, np.float64).ravel(), _c(u, np.float64).ravel(), M,
+                             _c(net.fibers, np.int32).ravel(), _c(net.EA, np.float64),
+                             _c(net.fixed, np.uint8), _c(F, np.float64).ravel(), C.byref(rho), sig, sigf)
+    if rc != 0:
+        raise ValueError("oracle_evaluate: invalid input (%d)" % rc)
+    return rho.value, sig.reshape(3, 3), sigf.reshape(3, 3)
 
 
 def solve(net, F, *, tol=1e-8, max_iter=2_000_000, beta, dt_safety,

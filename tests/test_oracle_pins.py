@@ -477,3 +477,25 @@ def test_step_rule_keeps_the_constant_step(oracle_lib):
             assert b.dt_min == a.dt == b.dt
             assert a.iters == b.iters and a.status == b.status
             assert np.array_equal(a.u, b.u) and np.array_equal(a.sigma, b.sigma)
+
+
+def test_evaluate_definitions(oracle_lib):
+    """The evaluation of a given state (residual of R6, stress of R7): at the
+    state a solve returns it reproduces the solve's own residual and stresses
+    bit for bit; at the affine state of the regular lattice the interior is
+    in equilibrium and the stress is the closed form."""
+    O = oracle_lib
+    b = I.small_batch(2, 80, 200, 0.02, seed=6)
+    for net, F in zip(b.nets, b.F):
+        r = O.solve(net, F, tol=1e-8, beta=BETA, dt_safety=S)
+        rho, s, sf = O.evaluate(net, F, r.u)
+        assert rho == r.rho and np.array_equal(s, r.sigma) and np.array_equal(sf, r.sigma_fib)
+    m = 3
+    lat = I.cubic_lattice(m, EA=1.3)
+    F = np.array([[1.05, 0.02, 0.0], [0.01, 1.03, 0.0], [0.0, 0.015, 1.04]])
+    rho, s, _ = O.evaluate(lat, F, lat.X @ (F - np.eye(3)).T)
+    J = np.linalg.det(F)
+    sig = sum((m + 1) ** 2 / J * 1.3 * (np.linalg.norm(F[:, k]) ** 2 - 1) / (2 * np.linalg.norm(F[:, k]))
+              * np.outer(F[:, k], F[:, k]) for k in range(3))
+    assert rho < 1e-13
+    assert _rel(s, sig) < 1e-12
