@@ -52,9 +52,16 @@ MEASURED_TRAFFIC = {
 
 
 def kernels_digest():
+    """Digest of every device source (the kernels, their templates and the
+    data layout), in file-name order."""
+    import glob
     import hashlib
-    with open(os.path.join(ROOT, "paper_2305_07030_amd", "csrc", "dr_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2305_07030_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(workload):

@@ -16,9 +16,13 @@ value here comes from the HIP path.  The files it writes:
   uneven1024_sample.json   the 1024-network workload (N log-uniform in
       [2000, 33000], F = I + sym U(+-0.02), damping 1e-4): two networks of
       each default size class (register/LDS up to 6720 nodes, global above)
-      at tol 1e-8, with three perturbed starts each.
+      at tol 1e-8, with three perturbed starts each;
+  uneven1024_steprule.json   the four networks of that workload (indices
+      248, 278, 325, 425) whose constant-step solves diverge (a fiber
+      stretched beyond the step's headroom), solved with the per-pass step
+      (dt_rule 1) at tol 1e-8, with two perturbed starts each.
 
-Usage: python tests/golden/make_oracle_golden.py [uniform_sample|uniform_all|uneven_sample ...]
+Usage: python tests/golden/make_oracle_golden.py [uniform_sample|uniform_all|uneven_sample|uneven_steprule ...]
 (all three by default).  Runs one problem per thread on all host threads
 but one; the full set takes about an hour of CPU time per thread.
 """
@@ -58,19 +62,19 @@ def perturbed_start(net, F, k):
     return u0 + noise * (net.fixed == 0)[:, None]
 
 
-def solve_one(net, F, tol, k):
+def solve_one(net, F, tol, k, dt_rule=0):
     """k < 0: the plain affine start; k >= 0: perturbed start number k."""
-    kw = dict(tol=tol, max_iter=MAX_ITER, beta=BETA, dt_safety=DT_SAFETY)
+    kw = dict(tol=tol, max_iter=MAX_ITER, beta=BETA, dt_safety=DT_SAFETY, dt_rule=dt_rule)
     if k >= 0:
         kw.update(start=O.START_WARM, F_prev=F, u_prev=perturbed_start(net, F, k))
     t = time.perf_counter()
     r = O.solve(net, F, **kw)
     return dict(sigma=r.sigma.ravel().tolist(), sigma_fib=r.sigma_fib.ravel().tolist(),
-                iters=int(r.iters), rho=float(r.rho), status=int(r.status),
+                iters=int(r.iters), rho=float(r.rho), status=int(r.status), dt_min=float(r.dt_min),
                 seconds=round(time.perf_counter() - t, 2))
 
 
-def run_jobs(jobs, threads, label):
+def run_jobs(jobs, threads, label, dt_rule=0):
     """jobs: list of (key, net, F, tol, k, cost).  Longest first."""
     jobs = sorted(jobs, key=lambda j: -j[5])
     out = {}
@@ -79,7 +83,7 @@ def run_jobs(jobs, threads, label):
 
     def work(j):
         key, net, F, tol, k, _ = j
-        r = solve_one(net, F, tol, k)
+        r = solve_one(net, F, tol, k, dt_rule)
         done[0] += 1
         print(f"[{label}] {done[0]}/{len(jobs)} {key} tol {tol:g} start {k}: {r['iters']} passes, "
               f"status {r['status']}, {r['seconds']}s (t={time.perf_counter() - t0:.0f}s)", flush=True)
@@ -180,13 +184,37 @@ def uneven_sample(threads):
                 max_iter=MAX_ITER, perturbation=PERTURBATION, networks=nets)
 
 
+UNEVEN_DIVERGING = [248, 278, 325, 425]
+
+
+def uneven_steprule(threads):
+    ids = UNEVEN_DIVERGING
+    sub = I.config_uneven_batch(1024, idx=ids)
+    jobs = []
+    for k_net, i in enumerate(ids):
+        net, F = sub.nets[k_net], sub.F[k_net]
+        for k in [-1, 0, 1]:
+            jobs.append((i, net, F, 1e-8, k, net.n_fibers))
+    res = run_jobs(jobs, threads, "uneven-steprule", dt_rule=1)
+    nets = []
+    for k_net, i in enumerate(ids):
+        nets.append(dict(index=i, n_nodes=sub.nets[k_net].n_nodes, n_fibers=sub.nets[k_net].n_fibers,
+                         **{"tol_1e-08": dict(plain=res[(i, 1e-8, -1)],
+                                              perturbed=[res[(i, 1e-8, k)] for k in range(2)])}))
+    return dict(workload="1024 kNN(k=3) networks, N = round(exp U(ln 2000, ln 33000)), "
+                         "F = I + sym U(+-0.02), SeedSequence(3); per-pass step (dt_rule 1)",
+                damping=BETA, dt_safety=DT_SAFETY, max_iter=MAX_ITER, perturbation=PERTURBATION,
+                dt_rule=1, networks=nets)
+
+
 def main():
     what = sys.argv[1:] or ["uniform_sample", "uniform_all", "uneven_sample"]
     threads = max(1, int(os.environ.get("GOLDEN_THREADS", (os.cpu_count() or 2) - 1)))
     O.build(force=False)
     makers = dict(uniform_sample=(uniform_sample, "uniform256_sample.json"),
                   uniform_all=(uniform_all, "uniform256_all.json"),
-                  uneven_sample=(uneven_sample, "uneven1024_sample.json"))
+                  uneven_sample=(uneven_sample, "uneven1024_sample.json"),
+                  uneven_steprule=(uneven_steprule, "uneven1024_steprule.json"))
     for w in what:
         fn, name = makers[w]
         t = time.perf_counter()

@@ -6,6 +6,7 @@ the same tolerance; pass counts within +-1; displacements at a fixed pass
 count equal to round-off.  Inputs are the seeded synthetic networks of
 paper_2305_07030_amd.inputs.
 """
+import json
 import os
 import sys
 import time
@@ -202,57 +203,161 @@ def test_small_batch_converged_parity():
         assert rel(g["sigma"][i], o.sigma) < 1e-8, (i, rel(g["sigma"][i], o.sigma))
 
 
-def test_uniform_batch_full_size_sampled():
-    """The 256-network batch (N uniform in 1000..5000) in the launch the
-    benchmark times.  Every network is checked for properties that hold at
-    any size; three networks are re-solved by the oracle: at the benchmark's
-    tolerance 1e-8 (stress within 1e-7: both stopping states lie in the 1e-8
-    residual band) and, in the same launch shape, at 1e-10 (stress within
-    1e-8).  The oracle runs each to half the tolerance with its residual
-    trace, which gives both its own stopping pass and its residual at the
-    GPU's stopping pass."""
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Oracle results written by tests/golden/make_oracle_golden.py (which
+    calls only the oracle and the seeded input generators)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def oracle_spread(entry):
+    """How far the oracle's own stress moves between its plain run and its
+    runs from starts perturbed by 1e-15: the width of the set of results the
+    same iteration reaches under different rounding (the equilibrium of a
+    floppy network is not unique, and the stopping state lies anywhere in
+    the tolerance band)."""
+    s0 = np.array(entry["plain"]["sigma"])
+    return max(rel(np.array(q["sigma"]), s0) for q in entry["perturbed"])
+
+
+def stress_bar(entry):
+    """The parity bar on stress: 1e-8 relative, or 100x the oracle's own
+    spread where rounding alone moves the oracle further than that."""
+    return max(1e-8, 100.0 * oracle_spread(entry))
+
+
+def certify(net, F, u, sigma, tol):
+    """The oracle's own definitions evaluated at the state the GPU returned:
+    its residual (reading R6) must meet the tolerance and its stress
+    (reading R7) must be the GPU's, to rounding.  Returns (rho, stress
+    difference)."""
+    rho, s, _ = O.evaluate(net, F, u)
+    return rho, rel(sigma, s)
+
+
+def test_uniform_batch_stratified_oracle():
+    """The 256-network batch (N uniform in 1000..5000, damping 1e-4) in the
+    launch the benchmark times, against the oracle on a stratified sample of
+    16 networks (the five slowest to converge, the five largest, the three
+    smallest, three from the middle of the size range), at the benchmark's
+    tolerance 1e-8 and at 1e-10.
+
+    - Certificate, every sampled network and tolerance: at the GPU's returned
+      state the oracle's residual is within the tolerance (1 + 1e-6) and the
+      oracle's stress equals the GPU's within 1e-10.
+    - Stress against the oracle's own solve within the bar of stress_bar.
+      Where the GPU ends on another equilibrium than every oracle run (a
+      floppy network's equilibrium is not unique), the certificate is what
+      holds; the test reports such networks and allows at most one.
+    - Pass counts at tol 1e-8 within the range of the oracle's own runs
+      (plain and perturbed starts) widened by 0.2 % + 1 where that range is
+      narrow and the GPU ends on the oracle's equilibrium; the slow-mode
+      networks, whose pass counts move by up to 3x under a 1e-15
+      perturbation, are reported.
+    - Every network of the batch: rho <= tol, a symmetric stress, both stress
+      forms equal."""
+    G = golden("uniform256_sample.json")
     batch = I.config_uniform_batch(256)
     say("256-network batch, FP64, damping 1e-4: GPU solve")
     t = time.time()
-    b, g = gpu_solve(batch, tol=1e-8, damping=1e-4)
+    b, g = gpu_solve(batch, tol=1e-8, damping=G["damping"], want_u=True)
     say(f"GPU solve done in {time.time() - t:.1f}s; iters min/median/max",
         g["iters"].min(), int(np.median(g["iters"])), g["iters"].max())
     info = b.info()
-    say("launch", info)
+    b.close()
     assert (g["result"] == dr.DR_CONVERGED).all()
     assert (g["rho"] <= 1e-8).all()
     for i in range(len(batch)):
         s = g["sigma"][i]
         assert np.linalg.norm(s - s.T) < 1e-5 * np.linalg.norm(s)
         assert rel(g["sigma_fib"][i], s) < 1e-5
-    sizes = np.array([n.n_nodes for n in batch.nets])
-    sample = [int(i) for i in np.argsort(sizes)[:3]]
-    say("oracle on networks", sample, "N =", sizes[sample])
-    sub = batch.subset(sample)
-    os_ = oracle_all(sub, tol=0.5e-8, beta=1e-4, trace_len=1_500_000)
-    for k, i in enumerate(sample):
-        o = os_[k]
-        say(f"tol 1e-8, net {i}: passes gpu {g['iters'][i]} oracle {int(np.argmax(o.rho_trace <= 1e-8)) + 1}, "
-            f"oracle rho at the GPU's stop {o.rho_trace[min(int(g['iters'][i]), len(o.rho_trace)) - 1]:.3e}, "
-            f"sigma rel {rel(g['sigma'][i], o.sigma):.2e}")
-        assert o.status == O.CONVERGED
-        assert stops_alike(g["iters"][i], o, 1e-8)
-        assert rel(g["sigma"][i], o.sigma) < 1e-7
-    b.close()
-    b10 = dr.DRBatch(batch, tol=1e-10, damping=1e-4, dt_safety=S)
+    ids = [e["index"] for e in G["networks"]]
+    b10 = dr.DRBatch(batch, tol=1e-10, max_iter=G["max_iter"], damping=G["damping"], dt_safety=S)
     assert b10.info() == info
-    b10.solve(ids=np.array(sample, np.int32))
-    g10 = b10.results()
-    os10 = oracle_all(sub, tol=0.5e-10, beta=1e-4, trace_len=1_500_000)
-    for k, i in enumerate(sample):
-        o = os10[k]
-        say(f"tol 1e-10, net {i}: passes gpu {g10['iters'][k]} oracle "
-            f"{int(np.argmax(o.rho_trace <= 1e-10)) + 1}, oracle rho at the GPU's stop "
-            f"{o.rho_trace[min(int(g10['iters'][k]), len(o.rho_trace)) - 1]:.3e}, "
-            f"sigma rel {rel(g10['sigma'][k], o.sigma):.2e}")
-        assert o.status == O.CONVERGED and g10["result"][k] == dr.DR_CONVERGED
-        assert stops_alike(g10["iters"][k], o, 1e-10)
-        assert rel(g10["sigma"][k], o.sigma) < 1e-8
+    t = time.time()
+    b10.solve(ids=np.array(ids, np.int32))
+    g10 = b10.results(want_u=True)
+    b10.close()
+    say(f"tol 1e-10 solve of the sample done in {time.time() - t:.1f}s")
+    fails, elsewhere = [], set()
+    for k, e in enumerate(G["networks"]):
+        i = e["index"]
+        net, F = batch.nets[i], batch.F[i]
+        for tol, key, r, j in ((1e-8, "tol_1e-08", g, i), (1e-10, "tol_1e-10", g10, k)):
+            gs, gi, gr = r["sigma"][j], int(r["iters"][j]), r["result"][j]
+            ent = e[key]
+            o = ent["plain"]
+            crho, cerr = certify(net, F, r["u_list"][i], gs, tol)
+            if o["status"] != O.CONVERGED:
+                say(f"net {i:3d} tol {tol:g}: oracle stopped at max_iter ({o['iters']} passes), GPU {gi} "
+                    f"passes status {int(gr)}, oracle residual at the GPU's state {crho:.2e}: no converged "
+                    f"reference")
+                if cerr >= 1e-10:
+                    fails.append((i, tol, "certificate stress", cerr))
+                continue
+            err = rel(gs, np.array(o["sigma"]).reshape(3, 3))
+            bar = stress_bar(ent)
+            its = [o["iters"]] + [q["iters"] for q in ent["perturbed"]]
+            lo, hi = min(its), max(its)
+            narrow = hi <= 1.01 * lo
+            in_range = lo * (1 - 2e-3) - 1 <= gi <= hi * (1 + 2e-3) + 1
+            same = err < bar
+            say(f"net {i:3d} N={e['n_nodes']} ({e['why']}) tol {tol:g}: sigma rel {err:.2e} (bar {bar:.1e}, "
+                f"oracle spread {oracle_spread(ent):.1e}){'' if same else ' OTHER EQUILIBRIUM'}; oracle "
+                f"residual at the GPU's state {crho:.2e}, its stress there {cerr:.1e}; passes GPU {gi}, "
+                f"oracle {o['iters']} [{lo}, {hi}]{'' if narrow else ' (wide)'}")
+            if gr != dr.DR_CONVERGED or crho > tol * (1 + 1e-6) or cerr >= 1e-10:
+                fails.append((i, tol, "certificate", int(gr), crho, cerr))
+            if not same:
+                elsewhere.add(i)
+            if tol == 1e-8 and narrow and same and not in_range:
+                fails.append((i, tol, "passes", gi, (lo, hi)))
+    say("networks ending on another equilibrium than the oracle's:", sorted(elsewhere))
+    assert len(elsewhere) <= 1, sorted(elsewhere)
+    assert not fails, fails
+
+
+def test_uneven_batch_converged_per_class():
+    """The 1024-network batch (N log-uniform in [2000, 33000], damping 1e-4)
+    in its benchmark launch configuration (the default split: an LDS class
+    and a global class launched concurrently): networks of about 3000, 6000
+    (LDS class), 12000 and 24000 nodes (global class) solved to tol 1e-8
+    against the oracle: the certificate of certify (the oracle's residual at
+    the GPU's state within the tolerance, its stress there the GPU's) and
+    the stress within the bar of stress_bar (here the oracle's own runs from
+    1e-15-perturbed starts end on equilibria up to 7e-4 apart)."""
+    G = golden("uneven1024_sample.json")
+    batch = I.config_uneven_batch(1024)
+    ids = [e["index"] for e in G["networks"]]
+    b = dr.DRBatch(batch, tol=1e-8, damping=G["damping"], dt_safety=S)
+    cls = b.classes()
+    say("uneven batch classes", [(c["n_lo"], c["n_hi"], c["n_problems"]) for c in cls])
+    t = time.time()
+    b.solve(ids=np.array(ids, np.int32))
+    g = b.results(want_u=True)
+    b.close()
+    say(f"solved {ids} in {time.time() - t:.1f}s")
+    classes_seen = set()
+    for k, e in enumerate(G["networks"]):
+        ent = e["tol_1e-08"]
+        o = ent["plain"]
+        assert o["status"] == O.CONVERGED
+        cl = [c for c in range(len(cls)) if cls[c]["n_lo"] <= e["n_nodes"] <= cls[c]["n_hi"]][0]
+        classes_seen.add(cl)
+        err = rel(g["sigma"][k], np.array(o["sigma"]).reshape(3, 3))
+        its = [o["iters"]] + [q["iters"] for q in ent["perturbed"]]
+        i = e["index"]
+        crho, cerr = certify(batch.nets[i], batch.F[i], g["u_list"][i], g["sigma"][k], 1e-8)
+        say(f"net {i} N={e['n_nodes']} class {cl}: sigma rel {err:.2e} (bar {stress_bar(ent):.1e}), "
+            f"oracle residual at the GPU's state {crho:.2e}, its stress there {cerr:.1e}; "
+            f"passes GPU {int(g['iters'][k])}, oracle {o['iters']} [{min(its)}, {max(its)}]")
+        assert g["result"][k] == dr.DR_CONVERGED
+        assert crho <= 1e-8 * (1 + 1e-6) and cerr < 1e-10
+        assert err < stress_bar(ent)
+    assert classes_seen == set(range(len(cls)))
 
 
 def test_loop_comparator_matches_persistent():

@@ -8,7 +8,8 @@ the current stiffness, never growing back), through the C ABI.
   for the other kernels), the chain's bisection equilibrium at convergence.
 - A solve split over budgeted launches equals one launch, bit for bit.
 - The networks of the 1024-network workload whose constant-step solves
-  diverge converge with it, to the oracle's stress (stored oracle results).
+  diverge converge with it: to a state the oracle's own residual certifies
+  as an equilibrium, with the oracle's stress (stored oracle results).
 """
 import json
 import os
@@ -173,7 +174,11 @@ def test_diverging_uneven_networks_converge():
         spread = max(rel(np.array(q["sigma"]), s0) for q in e["tol_1e-08"]["perturbed"])
         bar = max(1e-8, 100 * spread)
         err = rel(g["sigma"][k].ravel(), s0)
+        # the oracle's residual and stress at the state the GPU returned
+        crho, cs, _ = O.evaluate(sub.nets[k], sub.F[k], g["u_list"][k])
         say(f"net {e['index']} N={e['n_nodes']}: passes GPU {int(g['iters'][k])}, oracle {o['iters']}, "
-            f"sigma rel {err:.2e} (bar {bar:.1e})")
+            f"sigma rel {err:.2e} (bar {bar:.1e}); oracle residual at the GPU's state {crho:.2e}, "
+            f"its stress there {rel(g['sigma'][k], cs):.1e}")
         assert o["status"] == O.CONVERGED and g["result"][k] == dr.DR_CONVERGED
+        assert crho <= 1e-8 * (1 + 1e-6) and rel(g["sigma"][k], cs) < 1e-10
         assert err < bar
