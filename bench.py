@@ -33,6 +33,11 @@ FLOP_PER_UPDATE = 38.0
 # (FP64: per free node u, v read+write 96 B; per node X 24 B, 1/m 8 B, row
 # pointer 4 B; per fiber 2 incidences x (4 B index + 16 B constants)).
 BYTES_PER_UPDATE = 104.0
+# The same for the FP32 state (per fiber 2 incidences x (4 B index + 16 B of
+# FP32 reference vector and constant); per free node the FP32 state with its
+# compensation terms and the velocity read and written; per node 1/m and the
+# row pointer): about 75 B per fiber-update.
+BYTES_PER_UPDATE_FP32 = 75.0
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_HBM = 8.0e12
 
@@ -557,7 +562,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "single", "uneven", "pool"])
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "uniform32", "single", "uneven", "pool"])
     ap.add_argument("--pool-size", type=int, default=4096, help="pool workload: resident networks")
     ap.add_argument("--requests", type=int, default=256, help="pool workload: closed-loop requests")
     ap.add_argument("--state-budget-mib", type=int, default=64,
@@ -602,9 +607,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dr.load()
+    prec, stall, bpu = dr.DR_FP64, 0, BYTES_PER_UPDATE
     if args.workload == "uniform":
         batch, beta, tol = I.config_uniform_batch(256), 1e-4, 1e-8
         wl = "256 kNN(k=3) fiber networks, N ~ U{1000..5000}, F = I + sym U(+-0.01), FP64, tol 1e-8"
+    elif args.workload == "uniform32":
+        # the same batch with FP32 nodal state and force gather (FP64 norms
+        # and stress), tol 1e-6, the stall guard on (see fp32_leg)
+        batch, beta, tol = I.config_uniform_batch(256), 1e-3, 1e-6
+        prec, stall, bpu = dr.DR_FP32, 50_000, BYTES_PER_UPDATE_FP32
+        wl = ("256 kNN(k=3) fiber networks, N ~ U{1000..5000}, F = I + sym U(+-0.01), FP32 state and "
+              "gather, FP64 norms and stress, tol 1e-6")
     else:
         batch, beta, tol = I.config_single(), 1e-3, 1e-8
         wl = "1 kNN(k=3) fiber network, N = 500, F = diag(1.01,1,1), FP64, tol 1e-8"
@@ -613,7 +626,7 @@ def main():
     stream = torch.cuda.current_stream()
     b = dr.DRBatch(batch, tol=tol, damping=beta, dt_safety=0.9, block=args.block,
                    placement=args.placement, tail_at=args.tail_at, tail_group=args.tail_group,
-                   stream=stream.cuda_stream)
+                   precision=prec, stall_window=stall, stream=stream.cuda_stream)
     info = b.info()
     log("launch:", info)
     Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
@@ -643,7 +656,7 @@ def main():
     value = updates / wall
     per_launch = updates / args.steps
     flops = FLOP_PER_UPDATE * per_launch / kern_s
-    hbm_equiv = BYTES_PER_UPDATE * per_launch / kern_s
+    hbm_equiv = bpu * per_launch / kern_s
     traffic = traffic_for(args.workload)
     ceil = ceilings()
     out = {
@@ -657,7 +670,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if prec == dr.DR_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": wl, "networks": len(batch), "fibers": int(M.sum()),
                    "damping": beta, "dt_safety": 0.9, "block": info["block"],
@@ -672,11 +685,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": hbm_equiv / 1e9, "peak": PEAK_HBM / 1e9,
                      "unit": "GB/s", "frac": hbm_equiv / PEAK_HBM,
                      "traffic": traffic,
-                     "achieved_is": "algorithmic bytes (104 B per fiber-update) / launch time",
+                     "achieved_is": f"algorithmic bytes ({bpu:g} B per fiber-update) / launch time",
                      "kernel": ("k_dr_reg" if info["nodes_per_thread"] > 0 else "k_dr_glb") +
                                (" + k_dr_glb group launch (tail hand-off)" if args.tail_at else ""),
                      "kernel_ms": kern_s * 1e3,
-                     "bytes_per_update": BYTES_PER_UPDATE,
+                     "bytes_per_update": bpu,
                      "measured_beyond_l2_GBps": traffic / kern_s / 1e9 if traffic else None,
                      "mall_copy_GBps": ceil["mall_copy_GBps"],
                      "hbm_copy_GBps": ceil["hbm_copy_GBps"],

@@ -307,6 +307,17 @@ dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int
                      int32_t n_ids, int64_t budget);
 
 /*
+ * As dr_advance with a pass budget per slot: slot k may make at most
+ * budgets[k] (>= 1) passes in this launch.  A scheduler gives slow problems
+ * (many fibers, global placement) smaller budgets than fast ones so that
+ * every slot of the launch finishes its budget at about the same time and no
+ * compute unit waits for the slowest.  Errors as dr_advance (DR_E_INVALID
+ * for budgets NULL or a budget < 1).
+ */
+dr_status dr_advance_each(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                          const int64_t *budgets, int32_t n_ids);
+
+/*
  * Waits for the batch's stream and returns the current results of the
  * listed problems (host array ids [n_ids]); any output may be NULL.  result
  * is DR_RUNNING for a solve still in progress (iters / resid / ke then
@@ -385,6 +396,16 @@ dr_status dr_batch_info(const dr_batch *b, int32_t *n_problems, int64_t *total_n
 dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor);
 
 /*
+ * The library's estimate of the time one DR pass of each problem takes alone
+ * on one compute unit, in the placement of its size class (seconds,
+ * [n_problems]; a model fitted to MI355X measurements: about 1.5 us + 0.65 ns
+ * per fiber in LDS placement, 2.2 us + 2.0 ns per fiber in global placement,
+ * 4.8 ns per fiber beyond 38k fibers).  Schedulers use it to size per-slot
+ * budgets (dr_advance_each); the serving pool does.  Host only.
+ */
+dr_status dr_batch_pass_costs(const dr_batch *b, double *seconds);
+
+/*
  * Size classes.  A batch splits its problems by node count into classes; each
  * class has one launch shape (threads per workgroup, nodes per thread, gather
  * chunk, placement) used for every solve of the batch, and the classes of a
@@ -452,7 +473,10 @@ void dr_batch_destroy(dr_batch *b);
  *                       (topology, masses and last displacements of every
  *                       network stay resident: they are the pool)
  *   max_slots           cap on in-flight solves (>= 1)
- *   tick_passes         DR passes per poll for every in-flight solve (>= 1)
+ *   tick_passes         DR passes per poll of the cheapest in-flight solve
+ *                       (>= 1); the others make as many as fit the same time
+ *                       by dr_batch_pass_costs (at least 1), so a tick's
+ *                       compute units finish together
  * Errors: as dr_batch_create, DR_E_INVALID for the caps (a budget below one
  * node's running state).
  */
@@ -475,8 +499,9 @@ dr_status dr_pool_submit(dr_pool *pool, int32_t id, const double *F, int64_t tag
  * One scheduling step: admits queued requests first come first served (a
  * request whose network is in flight waits without blocking the queue; one
  * that exceeds the slot or budget cap, or finds no free run of the arena
- * long enough for its network, blocks it), runs one launch of
- * tick_passes passes over every in-flight solve (new ones start, the others
+ * long enough for its network, blocks it), runs one launch over every
+ * in-flight solve (tick_passes passes for the cheapest, proportionally fewer
+ * for the slower ones; new ones start, the others
  * resume from their exact saved state: a result is the same bits as one
  * dr_solve with DR_START_WARM), waits for it, and retires the finished
  * solves.  Then returns up to max_out finished requests, oldest first (the

@@ -903,6 +903,12 @@ __device__ __forceinline__ void launch_done(const SolveArgs &A, const Slot &S, i
     }
 }
 
+// Passes problem p may make in this launch.
+__device__ __forceinline__ int64_t launch_budget(const SolveArgs &A, int p)
+{
+    return A.budgets ? A.budgets[p] : A.budget;
+}
+
 // Start of a new solve: F of the solve kept for resumes and the stress.
 __device__ __forceinline__ void begin_solve(const SolveArgs &A, const Slot &S)
 {
@@ -1053,6 +1059,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
     __syncthreads();
 
     const int64_t n0 = n;
+    const int64_t budget = launch_budget(A, S.p);
     const double tol2 = A.tol * A.tol;
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
@@ -1172,7 +1179,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
             drained = true; // the rest of this solve runs in a group launch
             break;
         }
-        if (n - n0 >= A.budget) break;
+        if (n - n0 >= budget) break;
         advance_all(tp);
         __syncthreads();
     }
@@ -1508,7 +1515,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     const int64_t n0 = n;
     // passes this launch may make: the budget counts from the first launch
     // of the batch call (a drained solve continues within the same budget)
-    const int64_t nlim = (GRP ? A.n_begin[S.p] : n0) + A.budget;
+    const int64_t nlim = (GRP ? A.n_begin[S.p] : n0) + launch_budget(A, S.p);
     const double tol2 = A.tol * A.tol;
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;

@@ -116,6 +116,7 @@ struct dr_batch {
     int64_t *d_n_begin = nullptr;
     double *d_gpart = nullptr;
     double *d_abuf = nullptr, *d_dt_next = nullptr; // per-pass time step (dt_rule = 1)
+    int64_t *d_budgets = nullptr, *h_budgets = nullptr; // per-problem pass budgets of a launch
     int32_t tail_group = 0;     // workgroups per handed-off problem (0: hand-off off)
     LaunchPlan tail_plan{};     // launch shape of the group kernel
     // caller-owned device workspace (dr_batch_create_in): every device array
@@ -173,11 +174,11 @@ void free_all(dr_batch *b)
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
                    b->d_e_work, b->d_e_damp, b->d_state_off, b->d_live, b->d_tail_list,
                    b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart,
-                   b->d_abuf, b->d_dt_next};
+                   b->d_abuf, b->d_dt_next, b->d_budgets};
     if (!b->ws)
         for (void *p : dev)
             if (p) (void)hipFree(p);
-    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars, b->h_state_off};
+    void *host[] = {b->h_F, b->h_ids, b->h_order, b->h_starts, b->h_scalars, b->h_state_off, b->h_budgets};
     for (void *p : host)
         if (p) (void)hipHostFree(p);
     if (b->staged) (void)hipEventDestroy(b->staged);
@@ -592,6 +593,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_gabort, drk::kTailMax)
     ZS(d_gbar, drk::kTailMax)
     ZS(d_n_begin, P)
+    ZS(d_budgets, P)
     ZS(d_gpart, (size_t)drk::kTailMax * 2 * drk::kGroupMax * 4)
     // with a caller-owned workspace the scatter comparator's force buffer is
     // carved up front (it is allocated on first use otherwise)
@@ -606,6 +608,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_starts), P * sizeof(int32_t), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_scalars), 8 * sizeof(double), 0));
     HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_state_off), P * sizeof(int64_t), 0));
+    HIPCHECK(hipHostMalloc(reinterpret_cast<void **>(&b->h_budgets), P * sizeof(int64_t), 0));
     HIPCHECK(hipEventCreateWithFlags(&b->staged, hipEventDisableTiming));
     HIPCHECK(hipStreamSynchronize(st));
     return DR_OK;
@@ -940,7 +943,7 @@ dr_status check_start(int32_t start, bool allow_resume)
 // order (the launch loop does not use it) and allocates no host memory
 // (last_ids holds n_problems from creation on).
 dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
-                int32_t n_ids, bool order_slots = true)
+                int32_t n_ids, bool order_slots = true, const int64_t *budgets = nullptr)
 {
     HIPCHECK(hipEventSynchronize(b->staged)); // previous staging consumed
     if (F) std::memcpy(b->h_F, F, 9 * sizeof(double) * (size_t)n_ids);
@@ -950,6 +953,7 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
         b->last_ids[k] = b->h_ids[k];
         b->h_order[k] = k;
         if (starts) b->h_starts[k] = starts[k];
+        if (budgets) b->h_budgets[b->h_ids[k]] = budgets[k];
     }
     // slots grouped by size class, largest problem first within a class
     if (order_slots)
@@ -973,6 +977,9 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
                             hipMemcpyHostToDevice, b->stream));
     if (starts)
         HIPCHECK(hipMemcpyAsync(b->d_starts, b->h_starts, sizeof(int32_t) * (size_t)n_ids,
+                                hipMemcpyHostToDevice, b->stream));
+    if (budgets)
+        HIPCHECK(hipMemcpyAsync(b->d_budgets, b->h_budgets, sizeof(int64_t) * (size_t)b->P,
                                 hipMemcpyHostToDevice, b->stream));
     if (b->state_off_dirty) {
         std::memcpy(b->h_state_off, b->state_off.data(), sizeof(int64_t) * (size_t)b->P);
@@ -1013,6 +1020,20 @@ dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sig
     // the stream is idle: refresh the host mirror of running solves
     for (size_t p = 0; p < P; ++p) b->running[p] = stt[p] == DR_RUNNING;
     return DR_OK;
+}
+
+// Estimated seconds per pass of problem p alone on one compute unit, in its
+// class's placement (MI355X measurements of one workgroup per problem): the
+// register/LDS variant about 1.5 us + 0.65 ns per fiber; the global
+// variant 2.2 us + 2.0 ns per fiber up to 38k fibers and 4.8 ns per fiber
+// beyond (its node records no longer stay in the L2 share of one CU).
+double pass_cost(const dr_batch *b, int32_t p)
+{
+    const double M = (double)b->hp[p].M;
+    const LaunchPlan &pl = b->classes[b->class_of[p]].plan;
+    if (pl.npt > 0 && b->opt.dt_rule == 0) return 1.5e-6 + 0.65e-9 * M;
+    if (M <= 37800.0) return 2.2e-6 + 2.0e-9 * M;
+    return 2.2e-6 + 2.0e-9 * 37800.0 + 4.8e-9 * (M - 37800.0);
 }
 
 // Launches the staged slots: one DR + stress launch per size class with
@@ -1356,14 +1377,20 @@ dr_status dr_solve_device(dr_batch *b, const double *F_device, const int32_t *id
     }
 }
 
-dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
-                     int32_t n_ids, int64_t budget)
+namespace {
+
+// dr_advance with one budget for every slot (budgets NULL) or one per slot.
+dr_status advance_impl(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                       int32_t n_ids, int64_t budget, const int64_t *budgets)
 {
     try {
         g_err.clear();
         if (!b) return fail(DR_E_INVALID, "batch is NULL");
         if (!F || !ids || !starts) return fail(DR_E_INVALID, "F, ids and starts are required");
-        if (budget < 1) return fail(DR_E_INVALID, "budget must be >= 1");
+        if (!budgets && budget < 1) return fail(DR_E_INVALID, "budget must be >= 1");
+        if (budgets)
+            for (int32_t k = 0; k < n_ids; ++k)
+                if (budgets[k] < 1) return fail(DR_E_INVALID, "budgets[%d] must be >= 1", k);
         dr_status s = check_ids(b, ids, n_ids);
         if (s != DR_OK) return s;
         for (int32_t k = 0; k < n_ids; ++k) {
@@ -1376,9 +1403,10 @@ dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int
                 return s;
             }
         }
-        if ((s = stage(b, F, ids, starts, n_ids)) != DR_OK) return s;
-        SolveArgs a = make_args(b, n_ids, DR_START_AFFINE, budget);
+        if ((s = stage(b, F, ids, starts, n_ids, true, budgets)) != DR_OK) return s;
+        SolveArgs a = make_args(b, n_ids, DR_START_AFFINE, budgets ? 1 : budget);
         a.starts = b->d_starts;
+        if (budgets) a.budgets = b->d_budgets;
         if ((s = launch_or_fail(b, a)) != DR_OK) return s;
         // Until dr_results reads the device status, every slot may still be running.
         for (int32_t k = 0; k < n_ids; ++k) b->running[ids[k]] = 1;
@@ -1387,6 +1415,21 @@ dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int
     } catch (...) {
         return fail(DR_E_INVALID, "unexpected exception in dr_advance");
     }
+}
+
+} // namespace
+
+dr_status dr_advance(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                     int32_t n_ids, int64_t budget)
+{
+    return advance_impl(b, F, ids, starts, n_ids, budget, nullptr);
+}
+
+dr_status dr_advance_each(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
+                          const int64_t *budgets, int32_t n_ids)
+{
+    if (!budgets) return fail(DR_E_INVALID, "budgets is NULL");
+    return advance_impl(b, F, ids, starts, n_ids, 0, budgets);
 }
 
 dr_status dr_results(dr_batch *b, const int32_t *ids, int32_t n_ids, double *sigma,
@@ -1708,6 +1751,15 @@ dr_status dr_graph_launch(dr_batch *b)
     }
 }
 
+dr_status dr_batch_pass_costs(const dr_batch *b, double *seconds)
+{
+    g_err.clear();
+    if (!b) return fail(DR_E_INVALID, "batch is NULL");
+    if (!seconds) return fail(DR_E_INVALID, "seconds is NULL");
+    for (int32_t p = 0; p < b->P; ++p) seconds[p] = pass_cost(b, p);
+    return DR_OK;
+}
+
 dr_status dr_batch_scalars(const dr_batch *b, double *dt, double *c, double *s_floor)
 {
     g_err.clear();
@@ -1841,16 +1893,24 @@ dr_status dr_pool_poll(dr_pool *pl, int32_t max_out, int64_t *tags, int32_t *ids
         const int32_t n = (int32_t)pl->active.size();
         if (n > 0) {
             std::vector<int32_t> slot_ids(n), starts(n), res(n);
-            std::vector<double> F(9 * (size_t)n), sig(9 * (size_t)n);
-            std::vector<int64_t> it(n);
+            std::vector<double> F(9 * (size_t)n), sig(9 * (size_t)n), cost(n);
+            std::vector<int64_t> it(n), budgets(n);
             int32_t k = 0;
+            double cmin = 1e300;
             for (auto &kv : pl->active) {
                 slot_ids[k] = kv.first;
                 starts[k] = kv.second.started ? DR_RESUME : DR_START_WARM;
                 std::memcpy(&F[9 * (size_t)k], kv.second.r.F, 9 * sizeof(double));
+                cost[k] = pass_cost(pl->b, kv.first);
+                cmin = std::min(cmin, cost[k]);
                 ++k;
             }
-            dr_status s = dr_advance(pl->b, F.data(), slot_ids.data(), starts.data(), n, pl->tick_passes);
+            // balanced tick: the cheapest solve makes tick_passes passes, the
+            // others as many as fit the same time, so the launch's compute
+            // units finish together instead of waiting for the slowest
+            for (k = 0; k < n; ++k)
+                budgets[k] = std::max<int64_t>(1, (int64_t)std::llround((double)pl->tick_passes * cmin / cost[k]));
+            dr_status s = advance_impl(pl->b, F.data(), slot_ids.data(), starts.data(), n, 0, budgets.data());
             if (s != DR_OK) return s;
             for (auto &kv : pl->active) kv.second.started = true;
             s = dr_results(pl->b, slot_ids.data(), n, sig.data(), nullptr, res.data(), it.data(), nullptr,

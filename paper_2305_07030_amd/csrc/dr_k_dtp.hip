@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
     __syncthreads();
 
     const int64_t n0 = n;
+    const int64_t budget = launch_budget(A, S.p);
     const double tol2 = A.tol * A.tol;
     double rho = 0.0, ke = 0.0, gf2 = 0.0, gb2 = 0.0, ke2 = 0.0;
     int status = kStatusRunning;
@@ -265,7 +266,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
         // update and displacement update (buffer n & 1 into (n + 1) & 1)
         dt = step_of(dt, A.dt_safety, w2);
         const double hn = 0.5 * dt;
-        const bool more = n - n0 < A.budget;
+        const bool more = n - n0 < budget;
         const GlbQ<double> src{qbuf_of(n)}, dst{qbuf_of(n + 1)};
         for (int r = tid; r < Nf; r += BLOCK) {
             double q[3];

@@ -86,6 +86,7 @@ struct SolveArgs {
     double tol;
     int64_t max_iter;         // cap on the passes of one solve
     int64_t budget;           // cap on the passes made in this launch
+    const int64_t *budgets;   // [P] per-problem cap for this launch (NULL: budget)
     int64_t stall_window;     // 0 = off, else passes without progress that end a solve
     double energy_tol;        // 0 = off, else the energy-balance check (enode, e_work, e_damp)
     // network (renumbered order)

@@ -27,9 +27,9 @@ _STATUS_NAMES = {DR_E_INVALID: "DR_E_INVALID", DR_E_NOMEM: "DR_E_NOMEM",
 # Every exported symbol of include/dr.h.
 EXPORTS = ("dr_options_default", "dr_batch_create", "dr_batch_workspace_bytes",
            "dr_batch_create_in", "dr_solve", "dr_solve_device",
-           "dr_stress", "dr_advance", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
+           "dr_stress", "dr_advance", "dr_advance_each", "dr_results", "dr_energy", "dr_sync", "dr_solve_loop",
            "dr_solve_loop_scatter", "dr_solve_loop_scatter_noalloc", "dr_batch_info",
-           "dr_batch_scalars", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
+           "dr_batch_scalars", "dr_batch_pass_costs", "dr_batch_class_info", "dr_set_class_plans", "dr_graph_capture",
            "dr_graph_launch", "dr_batch_destroy", "dr_pool_create", "dr_pool_submit", "dr_pool_poll",
            "dr_pool_status", "dr_pool_destroy", "dr_state_bytes_per_node", "dr_last_error")
 
@@ -121,6 +121,8 @@ def load():
     lib.dr_stress.restype = C.c_int
     lib.dr_advance.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64]
     lib.dr_advance.restype = C.c_int
+    lib.dr_advance_each.argtypes = [vp, vp, vp, vp, vp, C.c_int32]
+    lib.dr_advance_each.restype = C.c_int
     lib.dr_results.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
     lib.dr_results.restype = C.c_int
     lib.dr_energy.argtypes = [vp, vp, C.c_int32, vp, vp]
@@ -137,6 +139,8 @@ def load():
     lib.dr_batch_info.restype = C.c_int
     lib.dr_batch_scalars.argtypes = [vp, vp, vp, vp]
     lib.dr_batch_scalars.restype = C.c_int
+    lib.dr_batch_pass_costs.argtypes = [vp, vp]
+    lib.dr_batch_pass_costs.restype = C.c_int
     lib.dr_batch_class_info.argtypes = [vp, C.c_int32] + [vp] * 8
     lib.dr_batch_class_info.restype = C.c_int
     lib.dr_set_class_plans.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
@@ -246,11 +250,18 @@ def dr_solve_device(h: int, F_device_ptr: int, ids: Optional[np.ndarray], n_ids:
     _check(load().dr_solve_device(h, F_device_ptr, _ptr(idsa), int(n_ids), int(start)))
 
 
-def dr_advance(h: int, F: np.ndarray, ids: np.ndarray, starts: np.ndarray, budget: int):
+def dr_advance(h: int, F: np.ndarray, ids: np.ndarray, starts: np.ndarray, budget):
+    """budget: one pass budget for every slot (dr_advance) or an array of one
+    per slot (dr_advance_each)."""
     ids = np.ascontiguousarray(ids, np.int32)
     F = np.ascontiguousarray(F, np.float64).reshape(len(ids), 9)
     starts = np.ascontiguousarray(starts, np.int32)
-    _check(load().dr_advance(h, _ptr(F), _ptr(ids), _ptr(starts), len(ids), int(budget)))
+    if np.ndim(budget) == 0:
+        _check(load().dr_advance(h, _ptr(F), _ptr(ids), _ptr(starts), len(ids), int(budget)))
+    else:
+        bud = np.ascontiguousarray(budget, np.int64)
+        assert bud.shape == (len(ids),)
+        _check(load().dr_advance_each(h, _ptr(F), _ptr(ids), _ptr(starts), _ptr(bud), len(ids)))
 
 
 def dr_results(h: int, ids: np.ndarray) -> dict:
@@ -311,6 +322,12 @@ def dr_batch_info(h: int) -> dict:
                                 C.addressof(e), C.addressof(f)))
     return dict(n_problems=a.value, total_nodes=b.value, total_fibers=c.value, block=d.value,
                 lds_bytes=e.value, nodes_per_thread=f.value)
+
+
+def dr_batch_pass_costs(h: int, n_problems: int) -> np.ndarray:
+    out = np.zeros(n_problems)
+    _check(load().dr_batch_pass_costs(h, _ptr(out)))
+    return out
 
 
 def dr_batch_scalars(h: int, n_problems: int) -> dict:
@@ -527,6 +544,10 @@ class DRBatch:
 
     def scalars(self) -> dict:
         return dr_batch_scalars(self.h, self.P)
+
+    def pass_costs(self) -> np.ndarray:
+        """Estimated seconds per pass of each problem (dr_batch_pass_costs)."""
+        return dr_batch_pass_costs(self.h, self.P)
 
     def close(self):
         if self.h:

@@ -10,17 +10,20 @@ Scheduling is iteration-level continuous batching over the C ABI:
     the HBM budget for its running state, and no other request of the same
     network in flight;
   * every tick is one dr_advance launch over all in-flight slots (new ones
-    start warm, the others resume from their exact saved state) with a fixed
-    pass budget, so requests that arrive while others run join the next
-    launch and their work overlaps on the device;
+    start warm, the others resume from their exact saved state): the
+    cheapest in-flight solve makes tick_passes passes and the others as many
+    as fit the same time (the library's per-pass cost estimates), so the
+    launch's compute units finish together; requests that arrive while
+    others run join the next launch and their work overlaps on the device;
   * after the tick dr_results reports which solves finished; those retire,
     free their slot and budget, and their latency (arrival to result on the
     host) is recorded.
 A problem's arithmetic does not depend on what else is in the launch, so a
 result is the same, bit for bit, alone and in the mix.
 
-The device is any object with advance(ids, starts, budget, F), query(ids)
-and node_count(p); paper_2305_07030_amd.dr.DRBatch is the real one.
+The device is any object with advance(ids, starts, budgets, F), query(ids),
+node_count(p) and pass_cost(p); paper_2305_07030_amd.dr.DRBatch (wrapped by
+PoolDevice) is the real one.
 """
 from __future__ import annotations
 
@@ -127,7 +130,9 @@ class Server:
         starts = np.array([dr.DR_RESUME if self.started[n] else dr.DR_START_WARM for n in nets],
                           np.int32)
         F = np.stack([self.active[n].F for n in nets])
-        self.dev.advance(nets, starts, self.tick_passes, F=F)
+        cost = np.array([self.dev.pass_cost(int(n)) for n in nets])
+        budgets = np.maximum(1, np.rint(self.tick_passes * cost.min() / cost)).astype(np.int64)
+        self.dev.advance(nets, starts, budgets, F=F)
         for n in nets:
             self.started[n] = True
         q = self.dev.query(nets)
@@ -245,10 +250,14 @@ class PoolDevice:
         self.batch = batch
         self.b = dr.DRBatch(batch, **opts)
         self.N = np.array([n.n_nodes for n in batch.nets])
+        self.cost = self.b.pass_costs()
         self.bytes_per_node = state_bytes_per_node(opts.get("precision", dr.DR_FP64))
 
-    def advance(self, ids, starts, budget, F):
-        self.b.advance(ids, starts, budget, F=F)
+    def advance(self, ids, starts, budgets, F):
+        self.b.advance(ids, starts, budgets, F=F)
+
+    def pass_cost(self, p):
+        return self.cost[p]
 
     def query(self, ids):
         return self.b.query(ids)

@@ -86,3 +86,34 @@ def test_pool_rejections():
     out = pool.poll()
     assert len(out["tags"]) == 0
     pool.close()
+
+
+def test_advance_each_budgets():
+    """dr_advance_each: slot k makes exactly its own budget of passes; the
+    solves then resumed to a fixed total pass count give the same bits as one
+    launch (each problem's arithmetic does not depend on its budget)."""
+    batch = I.small_batch(4, 100, 2000, 0.02, seed=97)
+    K = 5000
+    kw = dict(tol=1e-300, max_iter=K, damping=1e-3, dt_safety=S)
+    ref = dr.DRBatch(batch, **kw)
+    ref.solve()
+    R = ref.results()
+    ref.close()
+    ids = np.arange(len(batch), dtype=np.int32)
+    b = dr.DRBatch(batch, **kw)
+    budgets = np.array([100, 250, 1000, 3000], np.int64)
+    b.advance(ids, np.full(len(ids), dr.DR_START_AFFINE, np.int32), budgets, F=batch.F)
+    q = b.query(ids)
+    say("after one launch:", q["iters"].tolist())
+    assert np.array_equal(q["iters"], budgets) and (q["result"] == dr.DR_RUNNING).all()
+    costs = b.pass_costs()
+    assert (costs > 0).all() and costs[np.argmax([n.n_fibers for n in batch.nets])] == costs.max()
+    for _ in range(100):
+        run = ids[b.query(ids)["result"] == dr.DR_RUNNING]
+        if len(run) == 0:
+            break
+        b.advance(run, np.full(len(run), dr.DR_RESUME, np.int32), np.full(len(run), 700, np.int64))
+    q = b.query(ids)
+    b.close()
+    assert (q["result"] == dr.DR_MAX_ITER).all() and (q["iters"] == K).all()
+    assert np.array_equal(q["sigma"], R["sigma"])

@@ -19,8 +19,9 @@ class FakeDevice:
     """Each solve needs a scripted number of passes; a tick advances every
     in-flight solve by the budget and costs `tick_cost` seconds."""
 
-    def __init__(self, sizes, need, clock, tick_cost=1.0):
+    def __init__(self, sizes, need, clock, tick_cost=1.0, cost=None):
         self.sizes = np.asarray(sizes)
+        self.cost = cost
         self.need = need
         self.clock = clock
         self.tick_cost = tick_cost
@@ -30,9 +31,14 @@ class FakeDevice:
     def node_count(self, p):
         return int(self.sizes[p])
 
-    def advance(self, ids, starts, budget, F):
+    def pass_cost(self, p):
+        return 1.0 if self.cost is None else float(self.cost[p])
+
+    def advance(self, ids, starts, budgets, F):
         self.launches.append(list(map(int, ids)))
+        self.budgets = dict(zip(map(int, ids), map(int, budgets)))
         for k, p in enumerate(ids):
+            budget = int(budgets[k])
             p = int(p)
             if starts[k] == dr.DR_RESUME:
                 st = self.state[p]
@@ -133,3 +139,16 @@ def test_request_stream_walks_F_symmetrically():
             assert np.abs(r.F - last[r.net]).max() <= 0.002 + 1e-15
         last[r.net] = r.F
     assert s.next_gap() > 0
+
+
+def test_balanced_tick_budgets():
+    """A tick gives the cheapest in-flight solve tick_passes passes and the
+    others as many as fit the same time by their per-pass cost."""
+    clock = FakeClock()
+    dev = FakeDevice([100, 200, 400], lambda p, F: 10 ** 6, clock, cost=[1.0, 2.0, 4.0])
+    srv = SV.Server(dev, hbm_budget_bytes=SV.state_bytes_per_node() * 10 ** 6, max_slots=3,
+                    tick_passes=800, clock=clock)
+    for p in range(3):
+        srv.submit(SV.Request(p, p, np.eye(3), 0.0))
+    srv.tick()
+    assert dev.budgets == {0: 800, 1: 400, 2: 200}
