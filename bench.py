@@ -188,14 +188,21 @@ def ceilings():
     return out
 
 
-def fp32_leg(batch, stream, beta=1e-3):
+# Damping of the FP32-state workloads: the FP32 residual floor falls steeply
+# with the damping (median floor on 64 networks of the 256-network batch,
+# MI355X: 1.0e-3 at 1e-4, 2.3e-4 at 3e-4, 3.5e-5 at 1e-3, 5.0e-6 at 3e-3,
+# 1.2e-6 at 1e-2, 1.0e-6 at 3e-2), and only from about 3e-2 on do most
+# solves reach tol 1e-6.
+FP32_DAMPING = 3e-2
+
+
+def fp32_leg(batch, stream, beta=FP32_DAMPING):
     """The same networks with FP32 nodal state and force gather (FP64 norms
     and stress), tol 1e-6 with a 50 000-pass stall guard, against an FP64
     solve of the same iteration (same damping, tol 1e-8).  FP32 rounding is
-    re-injected every pass and amplified by the lightly damped modes (about
-    1/sqrt(beta/2)), so this workload runs at beta = 1e-3, which keeps that
-    floor below the tolerance's scale; the FP64 workload's 1e-4 would leave
-    it near rho ~ 1e-3."""
+    re-injected every pass and the lightly damped modes integrate it, so the
+    residual it can reach falls steeply with the damping (FP32_DAMPING); the
+    FP64 workload's 1e-4 would leave it near rho ~ 1e-3."""
     import numpy as np
     import torch
 
@@ -384,9 +391,14 @@ def pool_main(args):
     from paper_2305_07030_amd import serve as SV
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     budget = args.state_budget_mib << 20
+    fp32 = args.precision == "fp32"
+    # FP32 state: tol 1e-6 and the damping at which its residual floor lies
+    # below it (see fp32_leg), the stall guard on
+    popt = (dict(tol=1e-6, damping=FP32_DAMPING, precision=dr.DR_FP32, stall_window=50_000) if fp32
+            else dict(tol=1e-8, damping=1e-4))
     t = time.perf_counter()
-    pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=256, tick_passes=4000, tol=1e-8,
-                   damping=1e-4, dt_safety=0.9)
+    pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=256, tick_passes=4000, dt_safety=0.9,
+                   **popt)
     log(f"pool created in {time.perf_counter() - t:.1f}s")
     stream = SV.RequestStream(batch.F, 0.0, 0.002, seed=50)
     reqs = [stream.make(0.0) for _ in range(args.requests)]
@@ -409,20 +421,84 @@ def pool_main(args):
                 f"{st['state_bytes'] >> 20} MiB of state")
             t_last = now
     wall = time.perf_counter() - t0
-    pool.close()
     lat = np.array(lat)
     upd = float(sum(M[n] * i for n, i in zip(nets, its)))
+    # saturated rate: completions between the 10th and the 90th percentile
+    # completion times (the queue is full then; the start-up and the drain,
+    # which the slowest solves set, are left out)
+    t10, t90 = np.percentile(lat, 10), np.percentile(lat, 90)
+    sat = 0.8 * len(lat) / max(t90 - t10, 1e-9)
+    seen = set(nets)
+    log(f"closed loop: {len(lat) / wall:.3f} solves/s overall, saturated {sat:.3f} solves/s, "
+        f"p50 {np.percentile(lat, 50):.1f}s, p99 {np.percentile(lat, 99):.1f}s")
+    open_loop = []
+    for frac in [float(x) for x in args.rates.split(",")] if args.rates else []:
+        r = pool_open_loop(pool, stream, frac * sat, args.warm, args.measure, args.open_limit, seen)
+        r["offered_fraction"] = frac
+        open_loop.append(r)
+        log(f"open loop at {frac} x saturation: {r}")
+    pool.close()
+    prec = "FP32 state, tol 1e-6, damping %g" % FP32_DAMPING if fp32 else "FP64, tol 1e-8, damping 1e-4"
     line = {"metric": "solves/s (serving pool, closed loop)", "value": len(lat) / wall, "unit": "solves/s",
-            "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "saturated_solves_per_s": sat,
+            "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if fp32 else "f64", "data": "synthetic",
             "config": {"workload": f"pool of {P} kNN(k=3) networks, N log-uniform [1000, 33000], "
-                                   f"F walk sym U(+-0.002), FP64, tol 1e-8, damping 1e-4, cold pool",
+                                   f"F walk sym U(+-0.002), {prec}, cold pool",
                        "requests": len(reqs), "state_budget_bytes": budget, "max_slots": 256,
-                       "tick_passes": 4000},
+                       "tick_passes": 4000, "ticks": "balanced (dr_batch_pass_costs)"},
+            "open_loop": open_loop,
             "wall_s": wall, "polls": polls, "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "fiber_updates_per_s": upd / wall,
             "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
             "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
     print(json.dumps(line), flush=True)
+
+
+def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen):
+    """Poisson arrivals at `rate` (wall clock) into the library's pool; each
+    poll submits the requests that have arrived, runs one tick and collects
+    the finished ones.  Latency = arrival to the result on the host; the
+    first n_warm requests are not measured.  `seen`: networks solved before
+    (their requests start warm); updated."""
+    import numpy as np
+
+    from paper_2305_07030_amd import dr
+    stream.rate = rate
+    t0 = time.perf_counter()
+    t_next = t0 + stream.next_gap()
+    arrival, lat, res = {}, [], []
+    issued = done = warm = 0
+    total = n_warm + n_meas
+    while done < total and time.perf_counter() - t0 < max_wall:
+        now = time.perf_counter()
+        while issued < total and t_next <= now:
+            r = stream.make(t_next)
+            if issued >= n_warm and r.net in seen:
+                warm += 1
+            seen.add(r.net)
+            pool.submit(r.net, r.F, issued)
+            arrival[issued] = t_next
+            issued += 1
+            t_next += stream.next_gap()
+        st = pool.status()
+        if st["queued"] == 0 and st["in_flight"] == 0 and st["completed"] == 0:
+            time.sleep(max(0.0, min(t_next - time.perf_counter(), 0.05)))
+            continue
+        out = pool.poll()
+        now = time.perf_counter()
+        for tag, rr in zip(out["tags"], out["result"]):
+            done += 1
+            if tag >= n_warm:
+                lat.append(now - arrival[int(tag)])
+                res.append(int(rr))
+    wall = time.perf_counter() - t0
+    lat = np.array(lat) if lat else np.zeros(1)
+    return {"offered_per_s": rate, "measured": len(res), "measured_warm_starts": warm, "issued": issued,
+            "completed": done,
+            "throughput_per_s": done / wall, "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "wall_s": wall,
+            "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
+            "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
 
 
 def uneven_main(args):
@@ -521,18 +597,69 @@ def uneven_main(args):
                      "kernel_ms": kern_s * 1e3, "bytes_per_update": BYTES_PER_UPDATE},
     }
     if args.converge:
-        out["converge"] = uneven_converge(batch, plans, beta, M, args.converge_limit)
+        out["converge"] = uneven_converge(batch, plans, beta, M, args.converge_limit, args.tail_at,
+                                          args.tail_group)
     print(json.dumps(out), flush=True)
 
 
-def uneven_converge(batch, plans, beta, M, limit_s):
+def uneven_leg(passes=20000):
+    """The 1024-network workload (N log-uniform in [2000, 33000]) beside the
+    main line: one graph-captured step of `passes` passes on every network
+    with the library's default plans (after one untimed step), timed with
+    HIP events on the batch stream."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import inputs as I
+    t = time.perf_counter()
+    batch = I.config_uneven_batch(1024)
+    M = np.array([n.n_fibers for n in batch.nets], np.float64)
+    gen = time.perf_counter() - t
+    stream = torch.cuda.Stream()
+    Fd = torch.tensor(batch.F.reshape(-1, 9), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b = dr.DRBatch(batch, tol=1e-300, max_iter=passes, damping=1e-4, dt_safety=0.9,
+                       stream=stream.cuda_stream)
+        b.graph_capture(Fd)
+        b.graph_launch()
+        b.results()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        b.graph_launch()
+        e1.record(stream)
+        r = b.results()
+        wall = time.perf_counter() - t0
+        classes = b.classes()
+        b.close()
+    upd = float((M * r["iters"]).sum())
+    kern = e0.elapsed_time(e1) / 1e3
+    out = {"workload": "1024 kNN(k=3) fiber networks, N = round(exp U(ln 2000, ln 33000)), "
+                       f"F = I + sym U(+-0.02), FP64, {passes} passes per network (fixed pass count), "
+                       "graph-captured step, default plans",
+           "value": upd / wall, "unit": "fiber-updates/s", "step_s": wall, "kernel_s": kern,
+           "nonfinite_before_K": int((r["result"] == dr.DR_NONFINITE).sum()),
+           "hbm_equivalent_frac": BYTES_PER_UPDATE * upd / kern / PEAK_HBM,
+           "classes": classes, "generation_s": gen}
+    log("uneven leg:", out)
+    return out
+
+
+def uneven_converge(batch, plans, beta, M, limit_s, tail_at=0, tail_group=0):
     """Every network to tol 1e-8 (max 2e6 passes) in launches of at most
-    100 000 passes each; the total wall time includes the host round trips."""
+    100 000 passes each (with tail_at > 0 the last tail_at running problems of
+    each launch move to workgroup groups); the networks whose constant-step
+    solve diverges are then solved with the per-pass step (dt_rule 1).  The
+    total wall time includes the host round trips and that second solve."""
     import numpy as np
 
     from paper_2305_07030_amd import dr
     from paper_2305_07030_amd import tune as T
-    b = dr.DRBatch(batch, tol=1e-8, max_iter=2_000_000, damping=beta, dt_safety=0.9)
+    b = dr.DRBatch(batch, tol=1e-8, max_iter=2_000_000, damping=beta, dt_safety=0.9,
+                   tail_at=tail_at, tail_group=tail_group)
     T.apply(b, plans)
     ids = np.arange(len(batch), dtype=np.int32)
     t0 = time.perf_counter()
@@ -545,14 +672,33 @@ def uneven_converge(batch, plans, beta, M, limit_s):
         if len(run) == 0 or el > limit_s:
             break
         b.advance(run, np.full(len(run), dr.DR_RESUME, np.int32), 100_000)
-    wall = time.perf_counter() - t0
-    it = q["iters"]
+    wall1 = time.perf_counter() - t0
+    it = q["iters"].copy()
+    res = q["result"].copy()
     b.close()
-    return {"wall_s": wall, "updates": float((M * it).sum()),
+    counts = lambda r: {name: int((r == code).sum()) for name, code in
+                        (("converged", dr.DR_CONVERGED), ("max_iter", dr.DR_MAX_ITER),
+                         ("nonfinite", dr.DR_NONFINITE), ("running", dr.DR_RUNNING))}
+    first = counts(res)
+    bad = ids[res == dr.DR_NONFINITE]
+    retry = None
+    if len(bad):
+        t1 = time.perf_counter()
+        rb = dr.DRBatch(batch.subset(bad), tol=1e-8, max_iter=2_000_000, damping=beta, dt_safety=0.9,
+                        dt_rule=1)
+        rb.solve()
+        r = rb.results()
+        rb.close()
+        it[bad] = r["iters"]
+        res[bad] = r["result"]
+        retry = {"networks": bad.tolist(), "seconds": time.perf_counter() - t1,
+                 "passes": r["iters"].tolist(), "result": r["result"].tolist()}
+        log(f"converge: per-pass step for {bad.tolist()}: {retry}")
+    wall = time.perf_counter() - t0
+    return {"wall_s": wall, "constant_step_wall_s": wall1, "updates": float((M * it).sum()),
             "value": float((M * it).sum()) / wall, "unit": "fiber-updates/s",
-            "status_counts": {name: int((q["result"] == code).sum()) for name, code in
-                              (("converged", dr.DR_CONVERGED), ("max_iter", dr.DR_MAX_ITER),
-                               ("nonfinite", dr.DR_NONFINITE), ("running", dr.DR_RUNNING))},
+            "status_counts_constant_step": first, "status_counts": counts(res),
+            "per_pass_step_retry": retry, "tail_at": tail_at, "tail_group": tail_group,
             "passes_median": int(np.median(it)), "passes_max": int(it.max()),
             "time_limit_s": limit_s}
 
@@ -565,8 +711,14 @@ def main():
     ap.add_argument("--workload", default="uniform", choices=["uniform", "uniform32", "single", "uneven", "pool"])
     ap.add_argument("--pool-size", type=int, default=4096, help="pool workload: resident networks")
     ap.add_argument("--requests", type=int, default=256, help="pool workload: closed-loop requests")
-    ap.add_argument("--state-budget-mib", type=int, default=64,
+    ap.add_argument("--state-budget-mib", type=int, default=160,
                     help="pool workload: running-state budget of in-flight solves")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"], help="pool workload")
+    ap.add_argument("--rates", default="",
+                    help="pool workload: open-loop offered rates as fractions of the closed-loop rate")
+    ap.add_argument("--warm", type=int, default=32, help="pool workload: open-loop unmeasured requests")
+    ap.add_argument("--measure", type=int, default=256, help="pool workload: open-loop measured requests")
+    ap.add_argument("--open-limit", type=float, default=400.0, help="pool workload: seconds per rate")
     ap.add_argument("--passes", type=int, default=20000,
                     help="uneven workload: passes per network per step")
     ap.add_argument("--no-tune", action="store_true",
@@ -584,6 +736,7 @@ def main():
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -614,7 +767,7 @@ def main():
     elif args.workload == "uniform32":
         # the same batch with FP32 nodal state and force gather (FP64 norms
         # and stress), tol 1e-6, the stall guard on (see fp32_leg)
-        batch, beta, tol = I.config_uniform_batch(256), 1e-3, 1e-6
+        batch, beta, tol = I.config_uniform_batch(256), FP32_DAMPING, 1e-6
         prec, stall, bpu = dr.DR_FP32, 50_000, BYTES_PER_UPDATE_FP32
         wl = ("256 kNN(k=3) fiber networks, N ~ U{1000..5000}, F = I + sym U(+-0.01), FP32 state and "
               "gather, FP64 norms and stress, tol 1e-6")
@@ -708,6 +861,8 @@ def main():
     if not args.no_fp32 and args.workload == "uniform":
         out["fp32"] = fp32_leg(batch, stream)
         log("fp32:", {k: v for k, v in out["fp32"].items() if k != "per_network_sigma_rel_err"})
+    if not args.no_uneven and args.workload == "uniform":
+        out["uneven"] = uneven_leg()
     if not args.no_serve and args.workload == "uniform":
         out["serving"] = serving_leg(batch, beta)
         log("serving:", out["serving"])

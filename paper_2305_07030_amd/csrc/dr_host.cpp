@@ -135,6 +135,10 @@ struct dr_batch {
     hipEvent_t staged = nullptr;
     // host mirror of which problems have a running solve (for DR_RESUME checks)
     std::vector<char> running;
+    // passes of each problem's last finished solve (0: none yet), for the
+    // launch order by estimated cost
+    std::vector<int64_t> last_passes;
+    std::vector<double> order_cost; // scratch of the launch order
     std::vector<char> seen; // [P] scratch of the id checks (all zero between calls)
     // last dr_solve* call
     int32_t last_n = -1;
@@ -938,8 +942,22 @@ dr_status check_start(int32_t start, bool allow_resume)
     return DR_OK;
 }
 
-// Stages F (may be NULL), ids, starts (may be NULL) and the largest-first
-// slot order, and uploads them.  order_slots = false leaves the identity
+// Estimated seconds per pass of problem p alone on one compute unit, in its
+// class's placement (MI355X measurements of one workgroup per problem): the
+// register/LDS variant about 1.5 us + 0.65 ns per fiber; the global
+// variant 2.2 us + 2.0 ns per fiber up to 38k fibers and 4.8 ns per fiber
+// beyond (its node records no longer stay in the L2 share of one CU).
+double pass_cost(const dr_batch *b, int32_t p)
+{
+    const double M = (double)b->hp[p].M;
+    const LaunchPlan &pl = b->classes[b->class_of[p]].plan;
+    if (pl.npt > 0 && b->opt.dt_rule == 0) return 1.5e-6 + 0.65e-9 * M;
+    if (M <= 37800.0) return 2.2e-6 + 2.0e-9 * M;
+    return 2.2e-6 + 2.0e-9 * 37800.0 + 4.8e-9 * (M - 37800.0);
+}
+
+// Stages F (may be NULL), ids, starts (may be NULL), per-slot budgets (may
+// be NULL) and the costliest-first slot order, and uploads them.  order_slots = false leaves the identity
 // order (the launch loop does not use it) and allocates no host memory
 // (last_ids holds n_problems from creation on).
 dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t *starts,
@@ -955,13 +973,33 @@ dr_status stage(dr_batch *b, const double *F, const int32_t *ids, const int32_t 
         if (starts) b->h_starts[k] = starts[k];
         if (budgets) b->h_budgets[b->h_ids[k]] = budgets[k];
     }
-    // slots grouped by size class, largest problem first within a class
-    if (order_slots)
+    // slots grouped by size class; within a class the costliest first
+    // (section III: sub-problems converge at different rates): estimated
+    // time = pass time x passes of the problem's last solve (the mean over
+    // the problems that have one, for those that have none), then size
+    if (order_slots) {
+        double known = 0.0;
+        int64_t nk = 0;
+        for (int32_t k = 0; k < n_ids; ++k)
+            if (b->last_passes[b->h_ids[k]] > 0) {
+                known += (double)b->last_passes[b->h_ids[k]];
+                ++nk;
+            }
+        const double guess = nk > 0 ? known / (double)nk : 1.0;
+        std::vector<double> &cost = b->order_cost;
+        cost.resize(b->P);
+        for (int32_t k = 0; k < n_ids; ++k) {
+            const int32_t p = b->h_ids[k];
+            cost[p] = pass_cost(b, p) * (b->last_passes[p] > 0 ? (double)b->last_passes[p] : guess);
+        }
         std::stable_sort(b->h_order, b->h_order + n_ids, [&](int32_t s, int32_t t) {
-            const int cs = b->class_of[b->h_ids[s]], ct = b->class_of[b->h_ids[t]];
+            const int32_t ps = b->h_ids[s], pt = b->h_ids[t];
+            const int cs = b->class_of[ps], ct = b->class_of[pt];
             if (cs != ct) return cs < ct;
-            return b->hp[b->h_ids[s]].N > b->hp[b->h_ids[t]].N;
+            if (cost[ps] != cost[pt]) return cost[ps] > cost[pt];
+            return b->hp[ps].N > b->hp[pt].N;
         });
+    }
     std::fill(b->slot_count.begin(), b->slot_count.end(), 0);
     for (int32_t k = 0; k < n_ids; ++k) ++b->slot_count[b->class_of[b->h_ids[k]]];
     for (size_t c = 0, off = 0; c < b->classes.size(); ++c) {
@@ -999,12 +1037,12 @@ dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sig
     const size_t P = (size_t)b->P;
     std::vector<double> sg, sf, rh, kk;
     std::vector<int32_t> stt(P);
-    std::vector<int64_t> it;
+    std::vector<int64_t> it(P);
     hipStream_t st = b->stream;
     if (sigma) { sg.resize(9 * P); HIPCHECK(hipMemcpyAsync(sg.data(), b->d_sigma, 9 * P * 8, hipMemcpyDeviceToHost, st)); }
     if (sigma_fib) { sf.resize(9 * P); HIPCHECK(hipMemcpyAsync(sf.data(), b->d_sigma_fib, 9 * P * 8, hipMemcpyDeviceToHost, st)); }
     HIPCHECK(hipMemcpyAsync(stt.data(), b->d_status, P * 4, hipMemcpyDeviceToHost, st));
-    if (iters) { it.resize(P); HIPCHECK(hipMemcpyAsync(it.data(), b->d_iters, P * 8, hipMemcpyDeviceToHost, st)); }
+    HIPCHECK(hipMemcpyAsync(it.data(), b->d_iters, P * 8, hipMemcpyDeviceToHost, st));
     if (resid) { rh.resize(P); HIPCHECK(hipMemcpyAsync(rh.data(), b->d_rho, P * 8, hipMemcpyDeviceToHost, st)); }
     if (ke) { kk.resize(P); HIPCHECK(hipMemcpyAsync(kk.data(), b->d_ke, P * 8, hipMemcpyDeviceToHost, st)); }
     HIPCHECK(hipStreamSynchronize(st));
@@ -1017,23 +1055,13 @@ dr_status gather_results(dr_batch *b, const int32_t *ids, int32_t n, double *sig
         if (resid) resid[k] = rh[p];
         if (ke) ke[k] = kk[p];
     }
-    // the stream is idle: refresh the host mirror of running solves
-    for (size_t p = 0; p < P; ++p) b->running[p] = stt[p] == DR_RUNNING;
+    // the stream is idle: refresh the host mirror of running solves and the
+    // pass counts of finished ones
+    for (size_t p = 0; p < P; ++p) {
+        b->running[p] = stt[p] == DR_RUNNING;
+        if (stt[p] != DR_RUNNING && stt[p] != drk::kStatusIdle && it[p] > 0) b->last_passes[p] = it[p];
+    }
     return DR_OK;
-}
-
-// Estimated seconds per pass of problem p alone on one compute unit, in its
-// class's placement (MI355X measurements of one workgroup per problem): the
-// register/LDS variant about 1.5 us + 0.65 ns per fiber; the global
-// variant 2.2 us + 2.0 ns per fiber up to 38k fibers and 4.8 ns per fiber
-// beyond (its node records no longer stay in the L2 share of one CU).
-double pass_cost(const dr_batch *b, int32_t p)
-{
-    const double M = (double)b->hp[p].M;
-    const LaunchPlan &pl = b->classes[b->class_of[p]].plan;
-    if (pl.npt > 0 && b->opt.dt_rule == 0) return 1.5e-6 + 0.65e-9 * M;
-    if (M <= 37800.0) return 2.2e-6 + 2.0e-9 * M;
-    return 2.2e-6 + 2.0e-9 * 37800.0 + 4.8e-9 * (M - 37800.0);
 }
 
 // Launches the staged slots: one DR + stress launch per size class with
@@ -1216,6 +1244,7 @@ dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_
     b->n_max = pk.n_max;
     b->desc = pk.desc;
     b->running.assign(b->P, 0);
+    b->last_passes.assign(b->P, 0);
     b->seen.assign(b->P, 0);
     b->last_ids.reserve(b->P);
     // running-state records: each problem at its node_base, or (a pool's
