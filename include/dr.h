@@ -167,7 +167,12 @@ typedef struct {
  *               arithmetic is the same as in one workgroup; only the residual
  *               norms are summed in another order, which could move the
  *               stopping pass only if their last bits decided the test.
- *               Not used under dr_graph_capture.
+ *               Not used under dr_graph_capture.  The group launch needs all
+ *               its workgroups resident at once: work from another batch or
+ *               stream that holds compute units meanwhile can keep members
+ *               out, and a group whose members do not all arrive within the
+ *               barrier's 2 s wait ends its problem with DR_ABORTED (no
+ *               kernel hangs).
  *   tail_group  0 = automatic (the most workgroups per problem, up to 16, that
  *               let tail_at problems be resident at once), else 2..16;
  *               DR_E_INVALID at creation when tail_at x tail_group workgroups
@@ -473,10 +478,12 @@ void dr_batch_destroy(dr_batch *b);
  *                       (topology, masses and last displacements of every
  *                       network stay resident: they are the pool)
  *   max_slots           cap on in-flight solves (>= 1)
- *   tick_passes         DR passes per poll of the cheapest in-flight solve
- *                       (>= 1); the others make as many as fit the same time
- *                       by dr_batch_pass_costs (at least 1), so a tick's
- *                       compute units finish together
+ *   tick_passes         length of a poll's launch, in DR passes of the pool's
+ *                       cheapest network (>= 1); every in-flight solve makes
+ *                       as many passes as fit that time by
+ *                       dr_batch_pass_costs (at least 1), so a tick's compute
+ *                       units finish together and a tick stays short whatever
+ *                       mix is in flight
  * Errors: as dr_batch_create, DR_E_INVALID for the caps (a budget below one
  * node's running state).
  */
@@ -500,8 +507,8 @@ dr_status dr_pool_submit(dr_pool *pool, int32_t id, const double *F, int64_t tag
  * request whose network is in flight waits without blocking the queue; one
  * that exceeds the slot or budget cap, or finds no free run of the arena
  * long enough for its network, blocks it), runs one launch over every
- * in-flight solve (tick_passes passes for the cheapest, proportionally fewer
- * for the slower ones; new ones start, the others
+ * in-flight solve (as many passes as fit tick_passes passes of the pool's
+ * cheapest network; new ones start, the others
  * resume from their exact saved state: a result is the same bits as one
  * dr_solve with DR_START_WARM), waits for it, and retires the finished
  * solves.  Then returns up to max_out finished requests, oldest first (the
