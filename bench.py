@@ -406,11 +406,16 @@ def pool_main(args):
     for r in reqs:
         pool.submit(r.net, r.F, r.rid)
     lat, res, its, nets, polls = [], [], [], [], 0
+    tick_s, tick_flight = [], []
     t_last = t0
     while len(lat) < len(reqs):
+        flight = pool.status()["in_flight"] + min(pool.status()["queued"], 256)
+        tp = time.perf_counter()
         out = pool.poll()
         polls += 1
         now = time.perf_counter()
+        tick_s.append(now - tp)
+        tick_flight.append(flight)
         lat += [now - t0] * len(out["tags"])
         res += out["result"].tolist()
         its += out["iters"].tolist()
@@ -432,8 +437,10 @@ def pool_main(args):
     log(f"closed loop: {len(lat) / wall:.3f} solves/s overall, saturated {sat:.3f} solves/s, "
         f"p50 {np.percentile(lat, 50):.1f}s, p99 {np.percentile(lat, 99):.1f}s")
     open_loop = []
+    tag0 = len(reqs)
     for frac in [float(x) for x in args.rates.split(",")] if args.rates else []:
-        r = pool_open_loop(pool, stream, frac * sat, args.warm, args.measure, args.open_limit, seen)
+        r = pool_open_loop(pool, stream, frac * sat, args.warm, args.measure, args.open_limit, seen, tag0)
+        tag0 += args.warm + args.measure
         r["offered_fraction"] = frac
         open_loop.append(r)
         log(f"open loop at {frac} x saturation: {r}")
@@ -447,19 +454,28 @@ def pool_main(args):
                        "requests": len(reqs), "state_budget_bytes": budget, "max_slots": 256,
                        "tick_passes": 4000, "ticks": "balanced (dr_batch_pass_costs)"},
             "open_loop": open_loop,
-            "wall_s": wall, "polls": polls, "p50_s": float(np.percentile(lat, 50)),
+            "wall_s": wall, "polls": polls,
+            "poll_s": {"p10": float(np.percentile(tick_s, 10)), "p50": float(np.percentile(tick_s, 50)),
+                       "p90": float(np.percentile(tick_s, 90)), "max": float(np.max(tick_s)),
+                       "total": float(np.sum(tick_s))},
+            "in_flight_at_poll": {"p10": float(np.percentile(tick_flight, 10)),
+                                  "p50": float(np.percentile(tick_flight, 50)),
+                                  "p90": float(np.percentile(tick_flight, 90))},
+            "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "fiber_updates_per_s": upd / wall,
             "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
             "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
     print(json.dumps(line), flush=True)
 
 
-def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen):
+def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen, tag0):
     """Poisson arrivals at `rate` (wall clock) into the library's pool; each
     poll submits the requests that have arrived, runs one tick and collects
     the finished ones.  Latency = arrival to the result on the host; the
     first n_warm requests are not measured.  `seen`: networks solved before
-    (their requests start warm); updated."""
+    (their requests start warm); updated.  Tags start at tag0 (a result of an
+    earlier run that finishes during this one is not counted); the run drains
+    its own requests for at most 60 s after its last arrival."""
     import numpy as np
 
     from paper_2305_07030_amd import dr
@@ -469,15 +485,21 @@ def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen):
     arrival, lat, res = {}, [], []
     issued = done = warm = 0
     total = n_warm + n_meas
+    t_log = t0
     while done < total and time.perf_counter() - t0 < max_wall:
         now = time.perf_counter()
+        if now - t_log > 20:
+            st = pool.status()
+            log(f"open loop {rate:.2f}/s: t={now - t0:.0f}s, {issued} issued, {done} done, "
+                f"{st['in_flight']} in flight, {st['queued']} queued")
+            t_log = now
         while issued < total and t_next <= now:
             r = stream.make(t_next)
             if issued >= n_warm and r.net in seen:
                 warm += 1
             seen.add(r.net)
-            pool.submit(r.net, r.F, issued)
-            arrival[issued] = t_next
+            pool.submit(r.net, r.F, tag0 + issued)
+            arrival[tag0 + issued] = t_next
             issued += 1
             t_next += stream.next_gap()
         st = pool.status()
@@ -487,10 +509,14 @@ def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen):
         out = pool.poll()
         now = time.perf_counter()
         for tag, rr in zip(out["tags"], out["result"]):
+            if int(tag) not in arrival:
+                continue  # a request of an earlier run
             done += 1
-            if tag >= n_warm:
+            if tag >= tag0 + n_warm:
                 lat.append(now - arrival[int(tag)])
                 res.append(int(rr))
+        if issued >= total and now - t_next > 60:
+            break
     wall = time.perf_counter() - t0
     lat = np.array(lat) if lat else np.zeros(1)
     return {"offered_per_s": rate, "measured": len(res), "measured_warm_starts": warm, "issued": issued,
@@ -711,7 +737,7 @@ def main():
     ap.add_argument("--workload", default="uniform", choices=["uniform", "uniform32", "single", "uneven", "pool"])
     ap.add_argument("--pool-size", type=int, default=4096, help="pool workload: resident networks")
     ap.add_argument("--requests", type=int, default=256, help="pool workload: closed-loop requests")
-    ap.add_argument("--state-budget-mib", type=int, default=160,
+    ap.add_argument("--state-budget-mib", type=int, default=384,
                     help="pool workload: running-state budget of in-flight solves")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"], help="pool workload")
     ap.add_argument("--rates", default="",

@@ -1145,6 +1145,7 @@ struct dr_pool {
     std::map<int64_t, int64_t> free_runs; // arena: first record -> length of a free run
     int32_t max_slots = 0;
     int64_t tick_passes = 0;
+    double cost_min = 0.0;      // per-pass cost of the pool's cheapest network
     struct Req {
         int32_t id;
         int64_t tag;
@@ -1848,6 +1849,8 @@ dr_status dr_pool_create(const dr_networks *nets, const dr_options *opt, void *h
         pl->state_budget = state_budget_bytes;
         pl->max_slots = max_slots;
         pl->tick_passes = tick_passes;
+        pl->cost_min = 1e300;
+        for (int32_t p = 0; p < pl->P; ++p) pl->cost_min = std::min(pl->cost_min, pass_cost(b, p));
         *out = pl;
         return DR_OK;
     } catch (const std::bad_alloc &) {
@@ -1925,20 +1928,21 @@ dr_status dr_pool_poll(dr_pool *pl, int32_t max_out, int64_t *tags, int32_t *ids
             std::vector<double> F(9 * (size_t)n), sig(9 * (size_t)n), cost(n);
             std::vector<int64_t> it(n), budgets(n);
             int32_t k = 0;
-            double cmin = 1e300;
             for (auto &kv : pl->active) {
                 slot_ids[k] = kv.first;
                 starts[k] = kv.second.started ? DR_RESUME : DR_START_WARM;
                 std::memcpy(&F[9 * (size_t)k], kv.second.r.F, 9 * sizeof(double));
                 cost[k] = pass_cost(pl->b, kv.first);
-                cmin = std::min(cmin, cost[k]);
                 ++k;
             }
-            // balanced tick: the cheapest solve makes tick_passes passes, the
-            // others as many as fit the same time, so the launch's compute
-            // units finish together instead of waiting for the slowest
+            // balanced tick of a fixed length, tick_passes passes of the
+            // pool's cheapest network: every solve makes as many passes as
+            // fit that time, so the launch's compute units finish together
+            // instead of waiting for the slowest, and a tick stays short
+            // whatever mix of networks is in flight
             for (k = 0; k < n; ++k)
-                budgets[k] = std::max<int64_t>(1, (int64_t)std::llround((double)pl->tick_passes * cmin / cost[k]));
+                budgets[k] = std::max<int64_t>(
+                    1, (int64_t)std::llround((double)pl->tick_passes * pl->cost_min / cost[k]));
             dr_status s = advance_impl(pl->b, F.data(), slot_ids.data(), starts.data(), n, 0, budgets.data());
             if (s != DR_OK) return s;
             for (auto &kv : pl->active) kv.second.started = true;

@@ -10,10 +10,10 @@ Scheduling is iteration-level continuous batching over the C ABI:
     the HBM budget for its running state, and no other request of the same
     network in flight;
   * every tick is one dr_advance launch over all in-flight slots (new ones
-    start warm, the others resume from their exact saved state): the
-    cheapest in-flight solve makes tick_passes passes and the others as many
-    as fit the same time (the library's per-pass cost estimates), so the
-    launch's compute units finish together; requests that arrive while
+    start warm, the others resume from their exact saved state) of a fixed
+    length, tick_passes passes of the pool's cheapest network: every solve
+    makes as many passes as fit that time (the library's per-pass cost
+    estimates), so the launch's compute units finish together; requests that arrive while
     others run join the next launch and their work overlaps on the device;
   * after the tick dr_results reports which solves finished; those retire,
     free their slot and budget, and their latency (arrival to result on the
@@ -22,7 +22,7 @@ A problem's arithmetic does not depend on what else is in the launch, so a
 result is the same, bit for bit, alone and in the mix.
 
 The device is any object with advance(ids, starts, budgets, F), query(ids),
-node_count(p) and pass_cost(p); paper_2305_07030_amd.dr.DRBatch (wrapped by
+node_count(p), pass_cost(p) and cost_min(); paper_2305_07030_amd.dr.DRBatch (wrapped by
 PoolDevice) is the real one.
 """
 from __future__ import annotations
@@ -131,7 +131,7 @@ class Server:
                           np.int32)
         F = np.stack([self.active[n].F for n in nets])
         cost = np.array([self.dev.pass_cost(int(n)) for n in nets])
-        budgets = np.maximum(1, np.rint(self.tick_passes * cost.min() / cost)).astype(np.int64)
+        budgets = np.maximum(1, np.rint(self.tick_passes * self.dev.cost_min() / cost)).astype(np.int64)
         self.dev.advance(nets, starts, budgets, F=F)
         for n in nets:
             self.started[n] = True
@@ -258,6 +258,9 @@ class PoolDevice:
 
     def pass_cost(self, p):
         return self.cost[p]
+
+    def cost_min(self):
+        return float(self.cost.min())
 
     def query(self, ids):
         return self.b.query(ids)

@@ -34,6 +34,9 @@ class FakeDevice:
     def pass_cost(self, p):
         return 1.0 if self.cost is None else float(self.cost[p])
 
+    def cost_min(self):
+        return 1.0 if self.cost is None else float(min(self.cost))
+
     def advance(self, ids, starts, budgets, F):
         self.launches.append(list(map(int, ids)))
         self.budgets = dict(zip(map(int, ids), map(int, budgets)))
@@ -142,13 +145,14 @@ def test_request_stream_walks_F_symmetrically():
 
 
 def test_balanced_tick_budgets():
-    """A tick gives the cheapest in-flight solve tick_passes passes and the
-    others as many as fit the same time by their per-pass cost."""
+    """A tick lasts tick_passes passes of the pool's cheapest network; every
+    in-flight solve makes as many passes as fit that time by its per-pass
+    cost, whether or not the cheapest network is in flight."""
     clock = FakeClock()
-    dev = FakeDevice([100, 200, 400], lambda p, F: 10 ** 6, clock, cost=[1.0, 2.0, 4.0])
+    dev = FakeDevice([100, 200, 400, 50], lambda p, F: 10 ** 6, clock, cost=[1.0, 2.0, 4.0, 0.5])
     srv = SV.Server(dev, hbm_budget_bytes=SV.state_bytes_per_node() * 10 ** 6, max_slots=3,
                     tick_passes=800, clock=clock)
     for p in range(3):
         srv.submit(SV.Request(p, p, np.eye(3), 0.0))
     srv.tick()
-    assert dev.budgets == {0: 800, 1: 400, 2: 200}
+    assert dev.budgets == {0: 400, 1: 200, 2: 100}
