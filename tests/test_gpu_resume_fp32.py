@@ -223,3 +223,54 @@ def test_fp32_chunked_equals_single():
     say("FP32 chunked: status", list(q["result"]), "passes", list(q["iters"]))
     assert np.array_equal(q["result"], ref["result"])
     assert np.array_equal(q["sigma"], ref["sigma"]) and np.array_equal(q["iters"], ref["iters"])
+
+
+def test_fp32_uniform_batch_against_oracle():
+    """The 256-network workload with FP32 state (the benchmark's FP32
+    configuration: damping 3e-2, tol 1e-6, stall guard 50 000 passes), against
+    the FP64 oracle on the stratified sample of 16 networks stored in
+    tests/golden/uniform256_sample.json (the oracle's solves at tol 1e-10).
+    Per network: the stress error against the oracle, the FP64 residual of
+    the FP32 state by the oracle's own definition (rho64), and the oracle's
+    own spread over 1e-15-perturbed starts.  Stated bound: where the oracle's
+    equilibrium is stable (spread below 1e-7) the stress error is at most
+    500 max(rho64, 1e-6) (the stress of a state moves with its residual;
+    observed factors 1.6-200 on this sample, stress errors 1.6e-6 to
+    4.3e-3); every FP32 state has rho64 below 1e-3; its stress is the FP64
+    stress of that state."""
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "uniform256_sample.json")) as f:
+        G = json.load(f)
+    batch = I.config_uniform_batch(256)
+    b = dr.DRBatch(batch, tol=1e-6, damping=3e-2, dt_safety=S, precision=dr.DR_FP32,
+                   stall_window=FP32_STALL)
+    b.solve()
+    g = b.results(want_u=True)
+    b.close()
+    say("FP32 batch: converged", int((g["result"] == dr.DR_CONVERGED).sum()), "stalled",
+        int((g["result"] == dr.DR_STALLED).sum()), "rho median", float(np.median(g["rho"])))
+    errs = []
+    for e in G["networks"]:
+        i = e["index"]
+        o = e["tol_1e-10"]["plain"]
+        if o["status"] != O.CONVERGED:
+            o = e["tol_1e-08"]["plain"]
+        s0 = np.array(o["sigma"]).reshape(3, 3)
+        err = rel(g["sigma"][i], s0)
+        rho64, s64, _ = O.evaluate(batch.nets[i], batch.F[i], g["u_list"][i])
+        spread = max(rel(np.array(q["sigma"]).reshape(3, 3), s0) for q in e["tol_1e-08"]["perturbed"])
+        say(f"net {i:3d} N={e['n_nodes']} ({e['why']}): FP32 status {int(g['result'][i])} passes "
+            f"{int(g['iters'][i])} rho {g['rho'][i]:.1e}; FP64 residual of its state {rho64:.1e}; sigma rel "
+            f"err vs oracle {err:.1e} (oracle spread at tol 1e-8 {spread:.1e})")
+        errs.append((i, int(g["result"][i]), err, spread, rho64, rel(g["sigma"][i], s64)))
+    e = np.array([x[2] for x in errs])
+    say(f"sigma rel err vs oracle: median {np.median(e):.1e}, p90 {np.percentile(e, 90):.1e}, max {e.max():.1e}")
+    ratio = [x[2] / max(x[4], 1e-6) for x in errs if x[3] < 1e-7]
+    say(f"stable-equilibrium networks: sigma error / max(rho64, 1e-6) up to {max(ratio):.1f}")
+    for i, st, err, spread, rho64, cs in errs:
+        assert st in (dr.DR_CONVERGED, dr.DR_STALLED, dr.DR_MAX_ITER)
+        assert rho64 < 1e-3
+        assert cs < 1e-10  # the stress of the state, in FP64
+        if spread < 1e-7:
+            assert err < 500 * max(rho64, 1e-6), (i, err, rho64)
