@@ -272,72 +272,14 @@ def multistream_leg(batch, beta, n_nets=16, passes=20000):
     return out
 
 
-def serving_leg(batch, beta, n_closed=512, n_warm=64, n_meas=256):
-    """Continuous batching over the resident batch as the pool (FP64): a
-    closed-loop run gives the saturated solve rate; open-loop Poisson arrivals
-    at 0.5, 0.8 and 0.95 of it give p50/p99 latency and throughput."""
-    import numpy as np
-
-    from paper_2305_07030_amd import serve as SV
-    dev = SV.PoolDevice(batch, tol=1e-8, damping=beta, dt_safety=0.9)
-    budget = SV.state_bytes_per_node() * int(sum(n.n_nodes for n in batch.nets))
-
-    def mk():
-        return SV.Server(dev, hbm_budget_bytes=budget, max_slots=len(batch), tick_passes=4000)
-    F0 = batch.F.copy()
-    # warm the pool: every network solved once, so requests start warm
-    warm = mk()
-    for p in range(len(batch)):
-        warm.submit(SV.Request(-1 - p, p, F0[p], 0.0))
-    while not warm.idle():
-        warm.tick()
-    closed = SV.run_closed_loop(mk(), SV.RequestStream(F0, 0.0, 0.002, seed=50), n_closed)
-    sat = closed.summary()["throughput_per_s"]
-    out = {"pool": f"{len(batch)} networks (N ~ U{{1000..5000}}), FP64, tol 1e-8, warm starts, "
-                   f"F <- F + sym U(+-0.002) per request, tick = 4000 passes",
-           "saturated_solves_per_s": sat, "closed_loop": closed.summary(), "rates": []}
-    for frac in (0.5, 0.8, 0.95):
-        st = SV.run_open_loop(mk(), SV.RequestStream(F0, frac * sat, 0.002, seed=51), n_warm,
-                              n_meas, max_wall=120.0)
-        d = st.summary()
-        d["offered_per_s"] = frac * sat
-        out["rates"].append(d)
-    dev.b.close()
-    out["native_pool_closed_loop"] = native_pool_closed_loop(batch, beta, budget, F0, n_closed)
-    return out
-
-
-def native_pool_closed_loop(batch, beta, budget, F0, n_requests):
-    """The same closed loop (warm pool, every request queued at once, the same
-    request stream) through the library's own pool (dr_pool_*)."""
-    import numpy as np
-
-    from paper_2305_07030_amd import dr
-    from paper_2305_07030_amd import serve as SV
-    pool = dr.Pool(batch, state_budget_bytes=budget, max_slots=len(batch), tick_passes=4000,
-                   tol=1e-8, damping=beta, dt_safety=0.9)
-    for p in range(len(batch)):
-        pool.submit(p, F0[p], -1 - p)
-    while sum(pool.status()[k] for k in ("queued", "in_flight", "completed")) > 0:
-        pool.poll()
-    stream = SV.RequestStream(F0, 0.0, 0.002, seed=50)
-    t0 = time.perf_counter()
-    for _ in range(n_requests):
-        r = stream.make(t0)
-        pool.submit(r.net, r.F, r.rid)
-    lat, done, polls, conv = [], 0, 0, 0
-    while done < n_requests:
-        out = pool.poll()
-        polls += 1
-        now = time.perf_counter()
-        done += len(out["tags"])
-        conv += int((out["result"] == dr.DR_CONVERGED).sum())
-        lat += [now - t0] * len(out["tags"])
-    wall = time.perf_counter() - t0
-    pool.close()
-    lat = np.array(lat)
-    return {"completed": done, "polls": polls, "converged": conv, "throughput_per_s": done / wall,
-            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))}
+def serving_leg(pool_batch, n_closed=192, rates=(0.5, 0.8, 0.95), n_warm=16, n_meas=64):
+    """The serving configuration at its own size, shortened: the 4096-network
+    pool (FP64, tol 1e-8, 384 MiB of running state) through the library's
+    pool, a cold closed loop for the saturated rate and short open-loop runs
+    at fractions of it (pool_run; `--workload pool` runs the long form)."""
+    r = pool_run(pool_batch, False, 384 << 20, n_closed, list(rates), n_warm, n_meas, 90.0, drain_s=20.0)
+    r["counts"] = f"closed loop {n_closed} requests, open loop {n_warm} + {n_meas} per rate"
+    return r
 
 
 def copy_calibration(mib):
@@ -360,40 +302,44 @@ def _pool_part(a):
     return I.config_pool(P, idx=list(range(lo, hi)))
 
 
-def pool_main(args):
-    """The serving configuration at its own size: a resident pool of
-    --pool-size networks (N log-uniform in [1000, 33000], FP64, tol 1e-8)
-    served by the library's pool (dr_pool_*) with a running-state budget
-    below capacity, so that admission binds.  Closed loop: --requests
-    requests (the arrival stream's pool ids and F walk) queued at once on a
-    cold pool (each network's first request starts from the affine field);
-    reports the solve rate and the latency from enqueue to sigma on the
-    host."""
+def make_pool_batch(P):
+    """The serving pool's networks (N log-uniform in [1000, 33000], seed base
+    5), generated in worker processes: call before this process touches the
+    GPU."""
     from concurrent.futures import ProcessPoolExecutor
 
     import numpy as np
 
-    P = args.pool_size
+    from paper_2305_07030_amd import inputs as I
     t = time.perf_counter()
-    # networks generated in worker processes before this process touches the GPU
     cuts = np.linspace(0, P, 17).astype(int)
     with ProcessPoolExecutor(16) as ex:
         parts = list(ex.map(_pool_part, [(P, int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]))
-    from paper_2305_07030_amd import inputs as I
     batch = I.Batch([n for b in parts for n in b.nets], np.concatenate([b.F for b in parts]))
-    N = np.array([n.n_nodes for n in batch.nets])
-    M = np.array([n.n_fibers for n in batch.nets])
-    log(f"pool: {P} networks, {N.sum()} nodes, {M.sum()} fibers, generated in {time.perf_counter() - t:.1f}s")
+    log(f"pool: {P} networks, {batch.total_nodes} nodes, {batch.total_fibers} fibers, generated in "
+        f"{time.perf_counter() - t:.1f}s")
+    return batch
 
+
+def pool_run(batch, fp32, budget, n_requests, rates, warm, measure, open_limit, drain_s=60.0):
+    """The library's pool (dr_pool_*) over `batch` with a running-state budget
+    below capacity, so that admission binds.  Closed loop: n_requests
+    requests of the arrival stream (pool ids and F walk) queued at once on a
+    cold pool (a network's first request starts from the affine field), run
+    until 90 % are done: the saturated rate is the completions between the
+    10th and the 90th percentile times.  Then open-loop Poisson arrivals at
+    the given fractions of it (warm + measure requests each).  Latency =
+    enqueue (arrival) to sigma on the host."""
+    import numpy as np
     import torch
 
     from paper_2305_07030_amd import dr
     from paper_2305_07030_amd import serve as SV
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    budget = args.state_budget_mib << 20
-    fp32 = args.precision == "fp32"
-    # FP32 state: tol 1e-6 and the damping at which its residual floor lies
-    # below it (see fp32_leg), the stall guard on
+    P = len(batch)
+    M = np.array([n.n_fibers for n in batch.nets])
+    # FP32 state: tol 1e-6 at the damping where its residual floor lies below
+    # it (see fp32_leg), the stall guard on
     popt = (dict(tol=1e-6, damping=FP32_DAMPING, precision=dr.DR_FP32, stall_window=50_000) if fp32
             else dict(tol=1e-8, damping=1e-4))
     t = time.perf_counter()
@@ -401,15 +347,17 @@ def pool_main(args):
                    **popt)
     log(f"pool created in {time.perf_counter() - t:.1f}s")
     stream = SV.RequestStream(batch.F, 0.0, 0.002, seed=50)
-    reqs = [stream.make(0.0) for _ in range(args.requests)]
+    reqs = [stream.make(0.0) for _ in range(n_requests)]
     t0 = time.perf_counter()
     for r in reqs:
         pool.submit(r.net, r.F, r.rid)
     lat, res, its, nets, polls = [], [], [], [], 0
     tick_s, tick_flight = [], []
     t_last = t0
-    while len(lat) < len(reqs):
-        flight = pool.status()["in_flight"] + min(pool.status()["queued"], 256)
+    target = int(np.ceil(0.9 * n_requests))
+    while len(lat) < target:
+        st = pool.status()
+        flight = st["in_flight"] + min(st["queued"], 256)
         tp = time.perf_counter()
         out = pool.poll()
         polls += 1
@@ -420,7 +368,7 @@ def pool_main(args):
         res += out["result"].tolist()
         its += out["iters"].tolist()
         nets += out["ids"].tolist()
-        if now - t_last > 30:
+        if now - t_last > 20:
             st = pool.status()
             log(f"t={now - t0:.0f}s: {len(lat)} done, {st['in_flight']} in flight, {st['queued']} queued, "
                 f"{st['state_bytes'] >> 20} MiB of state")
@@ -428,54 +376,60 @@ def pool_main(args):
     wall = time.perf_counter() - t0
     lat = np.array(lat)
     upd = float(sum(M[n] * i for n, i in zip(nets, its)))
-    # saturated rate: completions between the 10th and the 90th percentile
-    # completion times (the queue is full then; the start-up and the drain,
-    # which the slowest solves set, are left out)
     t10, t90 = np.percentile(lat, 10), np.percentile(lat, 90)
-    sat = 0.8 * len(lat) / max(t90 - t10, 1e-9)
+    sat = 0.8 * len(lat) / max(t90 - t10, 1e-9) * (n_requests / len(lat))
     seen = set(nets)
-    log(f"closed loop: {len(lat) / wall:.3f} solves/s overall, saturated {sat:.3f} solves/s, "
-        f"p50 {np.percentile(lat, 50):.1f}s, p99 {np.percentile(lat, 99):.1f}s")
+    log(f"closed loop: saturated {sat:.3f} solves/s, first {len(lat)} of {n_requests} done in {wall:.1f}s, "
+        f"p50 {np.percentile(lat, 50):.1f}s")
     open_loop = []
     tag0 = len(reqs)
-    for frac in [float(x) for x in args.rates.split(",")] if args.rates else []:
-        r = pool_open_loop(pool, stream, frac * sat, args.warm, args.measure, args.open_limit, seen, tag0)
-        tag0 += args.warm + args.measure
+    for frac in rates:
+        r = pool_open_loop(pool, stream, frac * sat, warm, measure, open_limit, seen, tag0, drain_s)
+        tag0 += warm + measure
         r["offered_fraction"] = frac
         open_loop.append(r)
         log(f"open loop at {frac} x saturation: {r}")
     pool.close()
     prec = "FP32 state, tol 1e-6, damping %g" % FP32_DAMPING if fp32 else "FP64, tol 1e-8, damping 1e-4"
-    line = {"metric": "solves/s (serving pool, closed loop)", "value": len(lat) / wall, "unit": "solves/s",
+    return {"pool": f"{P} kNN(k=3) networks, N log-uniform [1000, 33000], F walk sym U(+-0.002), {prec}, "
+                    f"cold pool",
+            "state_budget_bytes": budget, "max_slots": 256, "tick_passes": 4000,
+            "ticks": "fixed length, budgets from dr_batch_pass_costs",
             "saturated_solves_per_s": sat,
-            "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if fp32 else "f64", "data": "synthetic",
-            "config": {"workload": f"pool of {P} kNN(k=3) networks, N log-uniform [1000, 33000], "
-                                   f"F walk sym U(+-0.002), {prec}, cold pool",
-                       "requests": len(reqs), "state_budget_bytes": budget, "max_slots": 256,
-                       "tick_passes": 4000, "ticks": "balanced (dr_batch_pass_costs)"},
-            "open_loop": open_loop,
-            "wall_s": wall, "polls": polls,
-            "poll_s": {"p10": float(np.percentile(tick_s, 10)), "p50": float(np.percentile(tick_s, 50)),
-                       "p90": float(np.percentile(tick_s, 90)), "max": float(np.max(tick_s)),
-                       "total": float(np.sum(tick_s))},
-            "in_flight_at_poll": {"p10": float(np.percentile(tick_flight, 10)),
-                                  "p50": float(np.percentile(tick_flight, 50)),
-                                  "p90": float(np.percentile(tick_flight, 90))},
-            "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "fiber_updates_per_s": upd / wall,
-            "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
-            "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
+            "closed_loop": {"requests": n_requests, "measured_until": len(lat), "wall_s": wall, "polls": polls,
+                            "p50_s": float(np.percentile(lat, 50)), "fiber_updates_per_s": upd / wall,
+                            "poll_s": {"p10": float(np.percentile(tick_s, 10)),
+                                       "p50": float(np.percentile(tick_s, 50)),
+                                       "p90": float(np.percentile(tick_s, 90)), "max": float(np.max(tick_s))},
+                            "in_flight_at_poll": {"p10": float(np.percentile(tick_flight, 10)),
+                                                  "p50": float(np.percentile(tick_flight, 50)),
+                                                  "p90": float(np.percentile(tick_flight, 90))},
+                            "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}},
+            "open_loop": open_loop}
+
+
+def pool_main(args):
+    """The serving configuration at its own size (--pool-size networks),
+    closed loop then open-loop rates (pool_run), as its own line."""
+    batch = make_pool_batch(args.pool_size)
+    rates = [float(x) for x in args.rates.split(",")] if args.rates else []
+    r = pool_run(batch, args.precision == "fp32", args.state_budget_mib << 20, args.requests, rates,
+                 args.warm, args.measure, args.open_limit)
+    line = {"metric": "solves/s (serving pool, saturated)", "value": r["saturated_solves_per_s"],
+            "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": r["pool"], "requests": args.requests}, **r}
     print(json.dumps(line), flush=True)
 
 
-def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen, tag0):
+def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen, tag0, drain_s=60.0):
     """Poisson arrivals at `rate` (wall clock) into the library's pool; each
     poll submits the requests that have arrived, runs one tick and collects
     the finished ones.  Latency = arrival to the result on the host; the
     first n_warm requests are not measured.  `seen`: networks solved before
     (their requests start warm); updated.  Tags start at tag0 (a result of an
     earlier run that finishes during this one is not counted); the run drains
-    its own requests for at most 60 s after its last arrival."""
+    its own requests for at most drain_s after its last arrival."""
     import numpy as np
 
     from paper_2305_07030_amd import dr
@@ -515,14 +469,14 @@ def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen, tag0):
             if tag >= tag0 + n_warm:
                 lat.append(now - arrival[int(tag)])
                 res.append(int(rr))
-        if issued >= total and now - t_next > 60:
+        if issued >= total and now - t_next > drain_s:
             break
     wall = time.perf_counter() - t0
     lat = np.array(lat) if lat else np.zeros(1)
     return {"offered_per_s": rate, "measured": len(res), "measured_warm_starts": warm, "issued": issued,
             "completed": done,
             "throughput_per_s": done / wall, "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "wall_s": wall,
+            "p90_s": float(np.percentile(lat, 90)), "p99_s": float(np.percentile(lat, 99)), "wall_s": wall,
             "converged": int(sum(r == dr.DR_CONVERGED for r in res)),
             "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
 
@@ -777,6 +731,10 @@ def main():
         return uneven_main(args)
     if args.workload == "pool":
         return pool_main(args)
+    # the serving leg's pool is generated in worker processes, before this
+    # process touches the GPU
+    pool_batch = (make_pool_batch(args.pool_size)
+                  if not args.no_serve and args.workload == "uniform" else None)
 
     import numpy as np
     import torch
@@ -890,7 +848,7 @@ def main():
     if not args.no_uneven and args.workload == "uniform":
         out["uneven"] = uneven_leg()
     if not args.no_serve and args.workload == "uniform":
-        out["serving"] = serving_leg(batch, beta)
+        out["serving"] = serving_leg(pool_batch)
         log("serving:", out["serving"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(batch, beta, tol)
