@@ -115,6 +115,7 @@ struct dr_batch {
     uint32_t *d_gbar = nullptr;
     int64_t *d_n_begin = nullptr;
     double *d_gpart = nullptr;
+    int32_t *d_gxcc = nullptr;
     double *d_abuf = nullptr, *d_dt_next = nullptr; // per-pass time step (dt_rule = 1)
     int64_t *d_budgets = nullptr, *h_budgets = nullptr; // per-problem pass budgets of a launch
     int32_t tail_group = 0;     // workgroups per handed-off problem (0: hand-off off)
@@ -177,7 +178,7 @@ void free_all(dr_batch *b)
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
                    b->d_e_work, b->d_e_damp, b->d_state_off, b->d_live, b->d_tail_list,
-                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart,
+                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart, b->d_gxcc,
                    b->d_abuf, b->d_dt_next, b->d_budgets};
     if (!b->ws)
         for (void *p : dev)
@@ -599,6 +600,7 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_n_begin, P)
     ZS(d_budgets, P)
     ZS(d_gpart, (size_t)drk::kTailMax * 2 * drk::kGroupMax * 4)
+    ZS(d_gxcc, (size_t)drk::kTailMax * drk::kGroupMax)
     // with a caller-owned workspace the scatter comparator's force buffer is
     // carved up front (it is allocated on first use otherwise)
     if (b->ws || b->counting) ZS(d_gscat, 3 * (size_t)std::max(pk.n_max, 1))
@@ -847,6 +849,7 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.gbar = b->d_gbar;
     a.gabort = b->d_gabort;
     a.gpart = b->d_gpart;
+    a.gxcc = b->d_gxcc;
     a.probs = b->d_probs;
     a.ids = b->d_ids;
     a.order = b->d_order;

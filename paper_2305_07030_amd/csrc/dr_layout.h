@@ -141,6 +141,7 @@ struct SolveArgs {
     uint32_t *gbar;           // [kTailMax] barrier counters of the groups
     int32_t *gabort;          // [kTailMax] abort flags of the groups
     double *gpart;            // [kTailMax * 2 * kGroupMax * 4] partial sums of the groups
+    int32_t *gxcc;            // [kTailMax * kGroupMax] XCD of each group member
     // per-pass time step (dt_rule = 1): the step's safety factor, the
     // acceleration records and the step of each running solve's next pass
     int32_t dt_rule;          // 0 = constant step, 1 = per-pass step (k_dr_dtp)
