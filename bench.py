@@ -481,6 +481,41 @@ def pool_open_loop(pool, stream, rate, n_warm, n_meas, max_wall, seen, tag0, dra
             "results": {str(k): int(sum(r == k for r in res)) for k in sorted(set(res))}}
 
 
+def resident_main(args):
+    """Bytes beyond L2 of the global-placement kernel against the number of
+    problems resident at once: `--copies` copies of one 16 000-node kNN
+    network (workgroups are dealt to the 8 XCDs round robin, so copies / 8
+    share one XCD's 4 MB L2), global placement, `--passes` fixed passes."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07030_amd import dr
+    from paper_2305_07030_amd import inputs as I
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rng = np.random.default_rng(7)
+    net = I.draw_network(rng, 16000)
+    F = I.sym_perturbed_F(rng, 0.02)
+    C, K = args.copies, args.passes
+    batch = I.Batch([net] * C, np.stack([F] * C))
+    b = dr.DRBatch(batch, tol=1e-300, max_iter=K, damping=1e-4, dt_safety=0.9, placement=dr.DR_PLACE_GLOBAL)
+    walls = []
+    for _ in range(2):
+        t = time.perf_counter()
+        b.solve()
+        r = b.results()
+        walls.append(time.perf_counter() - t)
+    b.close()
+    upd = float(C) * net.n_fibers * K
+    line = {"metric": "fiber-element updates/s (global placement, resident copies)", "value": upd / walls[-1],
+            "unit": "fiber-updates/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{C} copies of one 16000-node kNN(k=3) network, global placement, "
+                                   f"{K} passes", "copies": C, "nodes": net.n_nodes, "fibers": net.n_fibers,
+                       "passes": K},
+            "us_per_pass": walls[-1] / K * 1e6, "iters_min": int(r["iters"].min())}
+    print(json.dumps(line), flush=True)
+
+
 def uneven_main(args):
     """The 1024-network batch with node counts log-uniform in [2000, 33000]:
     launch shapes tuned per size bucket, the solve step captured in a HIP
@@ -664,14 +699,20 @@ def uneven_converge(batch, plans, beta, M, limit_s, tail_at=0, tail_group=0):
     retry = None
     if len(bad):
         t1 = time.perf_counter()
+        # with the tail hand-off on, these solves run in workgroup groups too
+        # (each group on one XCD; whole rounds of 8 groups must fit on the
+        # device's 256 compute units, one 1024-thread workgroup each)
+        G = min(16, 256 // (8 * ((len(bad) + 7) // 8))) if tail_at else 0
+        G = G if G >= 2 else 0
         rb = dr.DRBatch(batch.subset(bad), tol=1e-8, max_iter=2_000_000, damping=beta, dt_safety=0.9,
-                        dt_rule=1)
+                        dt_rule=1, tail_group=G)
         rb.solve()
         r = rb.results()
         rb.close()
         it[bad] = r["iters"]
         res[bad] = r["result"]
-        retry = {"networks": bad.tolist(), "seconds": time.perf_counter() - t1,
+        retry = {"networks": bad.tolist(), "workgroups_per_problem": G or 1,
+                 "seconds": time.perf_counter() - t1,
                  "passes": r["iters"].tolist(), "result": r["result"].tolist()}
         log(f"converge: per-pass step for {bad.tolist()}: {retry}")
     wall = time.perf_counter() - t0
@@ -688,7 +729,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "uniform32", "single", "uneven", "pool"])
+    ap.add_argument("--workload", default="uniform",
+                    choices=["uniform", "uniform32", "single", "uneven", "pool", "resident"])
+    ap.add_argument("--copies", type=int, default=256, help="resident workload: copies of the network")
     ap.add_argument("--pool-size", type=int, default=4096, help="pool workload: resident networks")
     ap.add_argument("--requests", type=int, default=256, help="pool workload: closed-loop requests")
     ap.add_argument("--state-budget-mib", type=int, default=384,
@@ -700,7 +743,7 @@ def main():
     ap.add_argument("--measure", type=int, default=256, help="pool workload: open-loop measured requests")
     ap.add_argument("--open-limit", type=float, default=400.0, help="pool workload: seconds per rate")
     ap.add_argument("--passes", type=int, default=20000,
-                    help="uneven workload: passes per network per step")
+                    help="uneven and resident workloads: passes per network per step")
     ap.add_argument("--no-tune", action="store_true",
                     help="uneven workload: skip the tuner (the library's default plans)")
     ap.add_argument("--converge", action="store_true",
@@ -731,6 +774,8 @@ def main():
         return uneven_main(args)
     if args.workload == "pool":
         return pool_main(args)
+    if args.workload == "resident":
+        return resident_main(args)
     # the serving leg's pool is generated in worker processes, before this
     # process touches the GPU
     pool_batch = (make_pool_batch(args.pool_size)

@@ -176,7 +176,15 @@ typedef struct {
  *   tail_group  0 = automatic (the most workgroups per problem, up to 16, that
  *               let tail_at problems be resident at once), else 2..16;
  *               DR_E_INVALID at creation when tail_at x tail_group workgroups
- *               cannot be resident at once.
+ *               cannot be resident at once.  With dt_rule 1 (which has no
+ *               hand-off): 2..16 runs every problem of a call in a group of
+ *               tail_group workgroups of 1024 threads from the start (one
+ *               cooperative launch, one size class; the same bits as one
+ *               workgroup per problem at a fixed pass count).  At most 256
+ *               problems per call (DR_E_DEVICE otherwise), and
+ *               8 x tail_group x ceil(n / 8) workgroups must fit on the
+ *               device at once (the runtime refuses the launch otherwise:
+ *               DR_E_DEVICE); size-class plans are DR_E_INVALID.
  *   dt_rule     0 = one constant step per solve (reading R3 of Fig. 1's
  *               "compute next time step"); 1 = a step per pass from the
  *               current state (reading R16): dt_n = min(dt_{n-1},

@@ -1248,31 +1248,16 @@ __global__ void __launch_bounds__(BLOCK) k_dr_reg(SolveArgs A)
 // the G partials in member order (the same lanes and order in every wave of
 // every member, so all take the same stop decision).  The wait is bounded:
 // a member that waits longer than kGroupTimeoutTicks marks the group
-// aborted and every member leaves its loop, so every kernel ends.
-//
-// Two forms of the barrier.  The general one releases and acquires at agent
-// scope, which on this chip writes back and invalidates the XCD's L2 (the
-// L2s of the 8 XCDs are not coherent with each other): correct wherever the
-// members run, but each pass then refetches the problem's state from beyond
-// L2.  When every member runs on one XCD (checked once per launch from the
-// XCC_ID hardware register) the members share one L2, and it is enough that
-// each wave's stores have reached it (the vector L1 writes through) before
-// the arrival is counted, and that each wave drops its L1 lines after the
-// wait: the local form.
+// aborted and every member leaves its loop, so every kernel ends.  Release
+// and acquire are at agent scope (on this chip an L2 write-back before the
+// arrival and an L2 invalidate after the wait).
 struct GroupCtx {
     uint32_t *bar;  // arrival counter of the group (0 at the launch)
     int32_t *abort; // nonzero once a member's wait timed out
     double *part;   // [2][kGroupMax][4] partial sums by barrier parity and member
     int G, member;
     uint32_t nbar;  // group barriers passed in this launch
-    bool local;     // every member on one XCD: the local form of the barrier
 };
-
-// The XCD this wave runs on (XCC_ID hardware register, bits 3:0).
-__device__ __forceinline__ int xcc_id()
-{
-    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
-}
 
 // 2 s of the 100 MHz wall clock.
 constexpr uint64_t kGroupTimeoutTicks = 200000000ull;
@@ -1281,11 +1266,9 @@ constexpr uint64_t kGroupTimeoutTicks = 200000000ull;
 // thread calls it; flag is an LDS word of the workgroup.
 __device__ __forceinline__ bool group_barrier(GroupCtx &gc, int *flag)
 {
-    // local form: this wave's stores have reached the L2 before the arrival
-    if (gc.local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads(); // the workgroup's writes of this phase are done
     if (threadIdx.x == 0) {
-        if (!gc.local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(gc.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = (gc.nbar + 1u) * (uint32_t)gc.G;
         int ok = 1;
@@ -1302,14 +1285,18 @@ __device__ __forceinline__ bool group_barrier(GroupCtx &gc, int *flag)
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (!gc.local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = ok;
     }
     __syncthreads();
-    // local form: later loads miss this compute unit's L1 and read the L2
-    if (gc.local) asm volatile("buffer_inv sc0" ::: "memory");
     ++gc.nbar;
     return *flag != 0;
+}
+
+// A value another member posted before the last group barrier.
+__device__ __forceinline__ double group_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sums K <= 4 workgroup totals (equal in every thread of a member) over the
@@ -1328,11 +1315,8 @@ __device__ __forceinline__ bool group_sum(GroupCtx &gc, int *flag, int lane, dou
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         // member m's value in lane m (G <= 16: one 16-lane row), zeros elsewhere
-        // (local form: a plain load, served by the shared L2)
         double t = 0.0;
-        if (lane < gc.G)
-            t = gc.local ? all[lane * 4 + k]
-                         : __hip_atomic_load(all + lane * 4 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane < gc.G) t = group_load(all + lane * 4 + k);
         v[k] = lane0(row_sum(t));
     }
     return ok;
@@ -1386,8 +1370,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     double *red = smem;
     int *gflag = reinterpret_cast<int *>(smem + NW * kRedStride);
     RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride + 2);
-    GroupCtx gc{nullptr, nullptr, nullptr, 1, 0, 0u, false};
-    int32_t *gxcc = nullptr; // XCDs of the group's members
+    GroupCtx gc{nullptr, nullptr, nullptr, 1, 0, 0u};
     Slot S;
     if constexpr (GRP) {
         const int b = blockIdx.x, G = A.group;
@@ -1398,8 +1381,6 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         gc.bar = A.gbar + g;
         gc.abort = A.gabort + g;
         gc.part = A.gpart + (int64_t)g * 2 * kGroupMax * 4;
-        gxcc = A.gxcc + (int64_t)g * kGroupMax;
-        if (tid == 0) gxcc[gc.member] = xcc_id(); // read back after the first barrier
         // a drained solve resumes from its saved state
         S.slot = -1;
         S.p = A.tail_list[g];
@@ -1573,18 +1554,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         }
     };
     advance_from(n);
-    if constexpr (GRP) {
-        alive = group_barrier(gc, gflag) && alive;
-        // the local barrier form once every member is known to share the XCD
-        // (the same values in every thread of every member)
-        bool same = true;
-        for (int m = 1; m < gc.G; ++m)
-            same = same && __hip_atomic_load(gxcc + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                               __hip_atomic_load(gxcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        gc.local = same;
-    } else {
-        __syncthreads();
-    }
+    if constexpr (GRP) alive = group_barrier(gc, gflag) && alive;
+    else __syncthreads();
     while (alive) {
         // pass n + 1 reads the state after pass n + 1's displacement update
         // (buffer (n + 1) & 1) and writes the next one into buffer n & 1;

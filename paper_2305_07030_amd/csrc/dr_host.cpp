@@ -115,7 +115,6 @@ struct dr_batch {
     uint32_t *d_gbar = nullptr;
     int64_t *d_n_begin = nullptr;
     double *d_gpart = nullptr;
-    int32_t *d_gxcc = nullptr;
     double *d_abuf = nullptr, *d_dt_next = nullptr; // per-pass time step (dt_rule = 1)
     int64_t *d_budgets = nullptr, *h_budgets = nullptr; // per-problem pass budgets of a launch
     int32_t tail_group = 0;     // workgroups per handed-off problem (0: hand-off off)
@@ -178,7 +177,7 @@ void free_all(dr_batch *b)
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
                    b->d_e_work, b->d_e_damp, b->d_state_off, b->d_live, b->d_tail_list,
-                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart, b->d_gxcc,
+                   b->d_tail_count, b->d_gabort, b->d_gbar, b->d_n_begin, b->d_gpart,
                    b->d_abuf, b->d_dt_next, b->d_budgets};
     if (!b->ws)
         for (void *p : dev)
@@ -600,7 +599,6 @@ dr_status create_device(dr_batch *b, Packed &pk)
     ZS(d_n_begin, P)
     ZS(d_budgets, P)
     ZS(d_gpart, (size_t)drk::kTailMax * 2 * drk::kGroupMax * 4)
-    ZS(d_gxcc, (size_t)drk::kTailMax * drk::kGroupMax)
     // with a caller-owned workspace the scatter comparator's force buffer is
     // carved up front (it is allocated on first use otherwise)
     if (b->ws || b->counting) ZS(d_gscat, 3 * (size_t)std::max(pk.n_max, 1))
@@ -720,9 +718,14 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         cls.push_back(c);
         lo = r.n_hi + 1;
     }
+    // the per-pass step in groups runs one launch per call: one class
+    const bool dtp_groups = b->opt.dt_rule == 1 && b->opt.tail_group > 1;
+    if (dtp_groups && !req.empty())
+        return fail(DR_E_INVALID, "the per-pass step in groups (dt_rule 1, tail_group > 1) runs one "
+                    "class; size-class plans do not apply");
     // automatic split of the rest
     const int32_t top = INT32_MAX;
-    if (b->opt.placement == DR_PLACE_GLOBAL || b->opt.placement == DR_PLACE_LDS) {
+    if (b->opt.placement == DR_PLACE_GLOBAL || b->opt.placement == DR_PLACE_LDS || dtp_groups) {
         dr_batch::Class c;
         c.n_lo = lo;
         c.n_hi = top;
@@ -845,11 +848,12 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.tail_list = b->d_tail_list;
     a.tail_count = b->d_tail_count;
     a.n_begin = b->d_n_begin;
-    a.group = b->tail_group;
+    // workgroups per problem: the tail hand-off's groups, or with the
+    // per-pass step every problem's group from the start
+    a.group = b->opt.dt_rule == 1 ? b->opt.tail_group : b->tail_group;
     a.gbar = b->d_gbar;
     a.gabort = b->d_gabort;
     a.gpart = b->d_gpart;
-    a.gxcc = b->d_gxcc;
     a.probs = b->d_probs;
     a.ids = b->d_ids;
     a.order = b->d_order;

@@ -22,6 +22,15 @@
 // velocity inside a pass) and the acceleration record.  A solve stopped by
 // the pass budget saves the next pass's step, so a resume continues with the
 // same bits.
+//
+// Group form (GRP): G workgroups per problem from the start of the launch,
+// one group per solve slot, as a cooperative launch.  The members act as one
+// virtual workgroup of G * BLOCK threads (node -> row -> wave as in the
+// group form of the global kernel, so every node's arithmetic is unchanged)
+// and meet at the group barrier twice per pass: after the reduction (the
+// norms summed over the members in member order, the stiffness bound as
+// their max, which is exact, so the steps and states are the same bits as
+// one workgroup's) and after the sweep.
 #include "dr_device.h"
 
 namespace drk {
@@ -117,14 +126,31 @@ __device__ __forceinline__ double step_of(double dt_prev, double safety, double 
     return dt < dt_prev ? dt : dt_prev;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool GRP = false>
 __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
 {
     constexpr int NW = BLOCK / kWave;
     __shared__ double red[NW * kRedStride];
+    __shared__ int gflag;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
-    const Slot S = load_slot(A, A.order ? A.order[blockIdx.x] : (int)blockIdx.x);
-    // a resume of a solve that is not running is a no-op (uniform per workgroup)
+    GroupCtx gc{nullptr, nullptr, nullptr, 1, 0, 0u};
+    int slot = (int)blockIdx.x;
+    if constexpr (GRP) {
+        // group g = solve slot g; its members are blockIdx values of one
+        // residue modulo 8 (one XCD)
+        const int b = blockIdx.x, G = A.group;
+        const int g = ((b >> 3) / G) * 8 + (b & 7);
+        if (g >= A.n_solve) return; // uniform per group
+        gc.G = G;
+        gc.member = (b >> 3) % G;
+        gc.bar = A.gbar + g;
+        gc.abort = A.gabort + g;
+        gc.part = A.gpart + (int64_t)g * 2 * kGroupMax * 4;
+        slot = g;
+    }
+    const Slot S = load_slot(A, A.order ? A.order[slot] : slot);
+    // a resume of a solve that is not running is a no-op (uniform per
+    // workgroup and group: no member writes the status before all have met)
     if (S.start == kResume && A.status[S.p] != kStatusRunning) return;
     const ProbDesc &P = S.P;
     const int N = P.N, Nf = P.N_free;
@@ -134,10 +160,24 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
     double *const W = A.wbuf + 3 * S.sb;
     double *const Acc = A.abuf + 3 * S.sb;
     const double dt0 = P.dt, cdamp = P.c;
+    // virtual workgroup: this thread's index, the stride, this wave's first node
+    const int VB = gc.G * BLOCK;
+    const int vt = gc.member * BLOCK + tid;
+    const int vbase = (gc.member * NW + wave) * kWave;
+    const bool lead = tid == 0 && gc.member == 0;
 
-    // Block reduction of two sums and one max; every thread gets the same
-    // bits (the sums as in the other kernels).  The caller guarantees a
-    // barrier since the last read of the records.
+    // Barrier of the workgroup, or of the group (false once the group was
+    // aborted).
+    bool alive = true;
+    auto sync = [&]() {
+        if constexpr (GRP) alive = group_barrier(gc, &gflag) && alive;
+        else __syncthreads();
+    };
+
+    // Reduction of two sums and one max over the workgroup, then over the
+    // group's members (sums in member order, max exact); every thread gets
+    // the same bits.  The caller guarantees a barrier since the last read
+    // of the records.
     auto reduce3 = [&](double &a, double &b, double &mx) {
         a = wave_sum(a);
         b = wave_sum(b);
@@ -157,23 +197,42 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
         a = lane0(row_sum(ta));
         b = lane0(row_sum(tb));
         mx = lane0(row_max(tm));
+        if constexpr (GRP) {
+            double *mine = gc.part + ((gc.nbar & 1u) * kGroupMax + gc.member) * 4;
+            if (tid == 0) {
+                mine[0] = a;
+                mine[1] = b;
+                mine[2] = mx;
+            }
+            sync();
+            const double *all = gc.part + ((gc.nbar - 1u) & 1u) * kGroupMax * 4;
+            double pa = 0.0, pb = 0.0, pm = 0.0;
+            if (lane < gc.G) {
+                pa = group_load(all + lane * 4 + 0);
+                pb = group_load(all + lane * 4 + 1);
+                pm = group_load(all + lane * 4 + 2);
+            }
+            a = lane0(row_sum(pa));
+            b = lane0(row_sum(pb));
+            mx = lane0(row_max(pm));
+        }
     };
 
     int64_t n = 0;
     double dt; // the step of the next pass
     if (S.start != kResume) {
         const GlbQ<double> q0{qbase};
-        for (int r = tid; r < N; r += BLOCK) {
+        for (int r = vt; r < N; r += VB) {
             double q[3];
             start_q<P64>(A, S, r, q);
             q0.store(r, q[0], q[1], q[2]);
         }
-        if (tid == 0) begin_solve(A, S);
-        __syncthreads();
+        if (lead) begin_solve(A, S);
+        sync();
         // initial force and acceleration (v = 0), the stiffness bound at the
         // start state, then the first half velocity update with its step
         double w2 = 0.0, z0 = 0.0, z1 = 0.0;
-        for (int base = wave * kWave; base < Nf; base += BLOCK) {
+        for (int base = vbase; base < Nf; base += VB) {
             const int r = base + lane;
             const Row row = node_row(A, P, base);
             double qi[3] = {0.0, 0.0, 0.0}, g[3], ks;
@@ -189,7 +248,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
         reduce3(z0, z1, w2);
         dt = step_of(dt0, A.dt_safety, w2);
         const double hdt = 0.5 * dt;
-        for (int r = tid; r < Nf; r += BLOCK)
+        for (int r = vt; r < Nf; r += VB)
 #pragma unroll
             for (int a = 0; a < 3; ++a) node_rec<3>(W, r)[a] = hdt * node_rec<3>(Acc, r)[a];
     } else {
@@ -202,7 +261,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
     // (n + 1) & 1; prescribed nodes are copied so that both buffers hold them
     {
         const GlbQ<double> src{qbuf_of(n)}, dst{qbuf_of(n + 1)};
-        for (int r = tid; r < N; r += BLOCK) {
+        for (int r = vt; r < N; r += VB) {
             double q[3];
             src.load(r, q[0], q[1], q[2]);
             if (r < Nf)
@@ -211,7 +270,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
             dst.store(r, q[0], q[1], q[2]);
         }
     }
-    __syncthreads();
+    sync();
 
     const int64_t n0 = n;
     const int64_t budget = launch_budget(A, S.p);
@@ -223,13 +282,13 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
         pg.best = A.rho_best[S.p];
         pg.nbest = A.n_best[S.p];
     }
-    for (;;) {
+    while (alive) {
         // pass n + 1 at the state in buffer (n + 1) & 1, with step dt
         const double hdt = 0.5 * dt;
         const GlbQ<double> pos{qbuf_of(n + 1)};
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         double w2 = 0.0;
-        for (int base = wave * kWave; base < N; base += BLOCK) {
+        for (int base = vbase; base < N; base += VB) {
             const int r = base + lane;
             const Row row = node_row(A, P, base);
             double qi[3] = {0.0, 0.0, 0.0}, g[3], ks;
@@ -260,6 +319,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
             }
         }
         reduce3(gf2, gb2, w2);
+        if (!alive) break;
         ++n;
         if (stop_test(A, P, tol2, gf2, gb2, n, status, pg)) break;
         // compute next time step, then the next pass's first half velocity
@@ -268,7 +328,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
         const double hn = 0.5 * dt;
         const bool more = n - n0 < budget;
         const GlbQ<double> src{qbuf_of(n)}, dst{qbuf_of(n + 1)};
-        for (int r = tid; r < Nf; r += BLOCK) {
+        for (int r = vt; r < Nf; r += VB) {
             double q[3];
             if (more) src.load(r, q[0], q[1], q[2]);
 #pragma unroll
@@ -280,20 +340,32 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
             if (more) dst.store(r, q[0], q[1], q[2]);
         }
         if (!more) break; // budget spent: the state after pass n stays in buffer n & 1
-        __syncthreads();
+        sync();
     }
-    // kinetic energy of the last pass (reported only)
-    ke2 = block_sum1<NW>(red, lane, wave, ke2);
+    if (!alive) status = kStatusAborted;
+    // kinetic energy of the last pass (reported only), once every wave has
+    // read the last reduction's records
+    __syncthreads();
+    if constexpr (GRP) {
+        if (alive) {
+            double z0 = 0.0, z1 = 0.0;
+            reduce3(ke2, z0, z1);
+            if (!alive) status = kStatusAborted;
+        }
+    } else {
+        ke2 = block_sum1<NW>(red, lane, wave, ke2);
+    }
     final_scalars(P, gf2, gb2, ke2, rho, ke);
-    if (status != kStatusRunning) {
+    if (status != kStatusRunning && status != kStatusAborted) {
+        // every node's final state was written by its own thread
         const GlbQ<double> fin{qbuf_of(n)};
-        for (int r = tid; r < N; r += BLOCK) {
+        for (int r = vt; r < N; r += VB) {
             double q[3];
             fin.load(r, q[0], q[1], q[2]);
             write_u<P64>(A, S, r, q);
         }
     }
-    if (tid == 0) {
+    if (lead) {
         record(A, S, n, rho, ke, status, pg);
         if (status == kStatusRunning) A.dt_next[S.p] = dt;
     }
@@ -302,6 +374,21 @@ __global__ void __launch_bounds__(BLOCK) k_dr_dtp(SolveArgs A)
 int launch_dtp(const SolveArgs &a, int block, void *stream)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (a.group > 1) {
+        // one group of a.group workgroups (1024 threads) per solve slot, all
+        // resident at once (the runtime refuses a larger cooperative grid)
+        if (a.n_solve > kTailMax) return -1003;
+        const int slots = 8 * ((a.n_solve + 7) / 8);
+        int rc = launch_fill_i32(reinterpret_cast<int32_t *>(a.gbar), 0, slots, stream);
+        if (rc == 0) rc = launch_fill_i32(a.gabort, 0, slots, stream);
+        if (rc != 0) return rc;
+        SolveArgs arg = a;
+        void *args[] = {&arg};
+        hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_dr_dtp<1024, true>),
+                                                  dim3(group_grid(a.n_solve, a.group)), dim3(1024), args, 0, st);
+        if (e != hipSuccess) return (int)e;
+        return (int)hipGetLastError();
+    }
     switch (block) {
     case 256: hipLaunchKernelGGL(k_dr_dtp<256>, dim3(a.n_solve), dim3(256), 0, st, a); break;
     case 512: hipLaunchKernelGGL(k_dr_dtp<512>, dim3(a.n_solve), dim3(512), 0, st, a); break;

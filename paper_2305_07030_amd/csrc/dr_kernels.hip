@@ -462,6 +462,7 @@ const char *kernel_error_string(int code)
     if (code == -1000) return "no kernel instantiated for this nodes-per-thread count";
     if (code == -1001) return "unsupported workgroup size";
     if (code == -1002) return "no global-placement kernel for this chunk at 256 threads";
+    if (code == -1003) return "a group launch of the per-pass step takes at most 256 problems per call";
     return hipGetErrorString((hipError_t)code);
 }
 

@@ -141,7 +141,6 @@ struct SolveArgs {
     uint32_t *gbar;           // [kTailMax] barrier counters of the groups
     int32_t *gabort;          // [kTailMax] abort flags of the groups
     double *gpart;            // [kTailMax * 2 * kGroupMax * 4] partial sums of the groups
-    int32_t *gxcc;            // [kTailMax * kGroupMax] XCD of each group member
     // per-pass time step (dt_rule = 1): the step's safety factor, the
     // acceleration records and the step of each running solve's next pass
     int32_t dt_rule;          // 0 = constant step, 1 = per-pass step (k_dr_dtp)
@@ -169,6 +168,8 @@ int launch_loop_kernels(const SolveArgs &a, int slot, int phase, int n_nodes, do
 int launch_fill_i32(int32_t *p, int32_t value, int64_t n, void *stream);
 // The per-pass time-step kernel (global placement, FP64) with `block`
 // threads per workgroup (256, 512 or 1024).
+// The per-pass step kernel; a.group > 1: its group form (a.group workgroups
+// of 1024 threads per solve slot, a cooperative launch).
 int launch_dtp(const SolveArgs &a, int block, void *stream);
 // The group launch of the tail hand-off (cooperative: all its workgroups are
 // co-resident) for up to n_groups handed-off problems, then the stress of the

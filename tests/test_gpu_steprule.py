@@ -182,3 +182,51 @@ def test_diverging_uneven_networks_converge():
         assert o["status"] == O.CONVERGED and g["result"][k] == dr.DR_CONVERGED
         assert crho <= 1e-8 * (1 + 1e-6) and rel(g["sigma"][k], cs) < 1e-10
         assert err < bar
+
+
+@pytest.mark.parametrize("group", [2, 4, 16])
+def test_group_form_same_bits(group):
+    """Every problem in a group of `group` workgroups from the start: at a
+    fixed pass count the same bits as one workgroup per problem (the step
+    bound is a max, exact in any order; sizes from one row per wave of the
+    group to several), also across budgeted launches."""
+    rng = np.random.default_rng(93)
+    nets = [I.draw_network(rng, n) for n in (300, 2600, 9000, 21000)]
+    base = I.Batch(nets, np.stack([np.diag([1.3, 1.0, 1.0])] * len(nets)))
+    K = 1500
+    kw = dict(tol=1e-300, max_iter=K, damping=1e-3, dt_rule=1)
+    ref = solve(base, start=dr.DR_START_ZERO, **kw)
+    got = solve(base, start=dr.DR_START_ZERO, tail_group=group, **kw)
+    say(f"group {group}: passes {got['iters'].tolist()}, results {got['result'].tolist()}")
+    assert np.array_equal(got["iters"], ref["iters"])
+    assert np.array_equal(got["result"], ref["result"])
+    assert np.array_equal(got["u"], ref["u"])
+    assert np.array_equal(got["sigma"], ref["sigma"])
+    # the same passes in budgeted group launches
+    ids = np.arange(len(base), dtype=np.int32)
+    b = dr.DRBatch(base, dt_safety=S, tail_group=group, **kw)
+    b.advance(ids, np.full(len(ids), dr.DR_START_ZERO, np.int32), 400, F=base.F)
+    for _ in range(10):
+        run = ids[b.query(ids)["result"] == dr.DR_RUNNING]
+        if len(run) == 0:
+            break
+        b.advance(run, np.full(len(run), dr.DR_RESUME, np.int32), 400)
+    q = b.query(ids)
+    b.close()
+    assert np.array_equal(q["iters"], ref["iters"])
+    assert np.array_equal(q["result"], ref["result"])
+    assert np.array_equal(q["sigma"], ref["sigma"])
+
+
+def test_group_form_converges_like_one_workgroup():
+    """To convergence the group sums the norms in member order, so its stop
+    pass may differ by one from one workgroup's; the stresses agree."""
+    batch = stretched_batch()
+    kw = dict(tol=1e-8, damping=1e-3, dt_rule=1)
+    ref = solve(batch, start=dr.DR_START_ZERO, **kw)
+    got = solve(batch, start=dr.DR_START_ZERO, tail_group=4, **kw)
+    say("passes", got["iters"].tolist(), "one workgroup", ref["iters"].tolist())
+    assert (got["result"] == dr.DR_CONVERGED).all()
+    assert np.abs(got["iters"].astype(np.int64) - ref["iters"]).max() <= 1
+    for i in range(len(batch)):
+        assert rel(got["sigma"][i], ref["sigma"][i]) < 1e-9
