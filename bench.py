@@ -47,12 +47,13 @@ PEAK_HBM = 8.0e12
 # and the commands).  Valid only for the kernel source it was measured on:
 # any change to the kernels makes the figure null until it is measured again.
 MEASURED_TRAFFIC = {
-    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7128695868.9 KiB x 1.9997 + WRITE 18355.5 KiB x 1.0
-    "uniform": {"kernels": "33702150a9af7593", "bytes_per_launch": 1.4597340e13},
-    # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels of one 20 000-pass launch (default
-    # plans); k_dr_glb FETCH 29370523181.1 KiB x 1.9997 + WRITE 8400492812.7 KiB, k_dr_reg
-    # FETCH 1493673366.2 KiB x 1.9997 + WRITE 58136.1 KiB
-    "uneven": {"kernels": "33702150a9af7593", "bytes_per_launch": 7.1802907e13},
+    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7.15524e9 KiB x 1.9998 + WRITE 18354.8 KiB x 1.0
+    "uniform": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 1.4652e13},
+    # profiles/k_dr_reg_uniform256_fp32.md: FETCH 6.92797e9 KiB x 1.9998 + WRITE 18356.4 KiB x 1.0
+    "uniform32": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 1.4187e13},
+    # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels and the stress of one 20 000-pass
+    # launch (default plans), per launch of the two the run makes
+    "uneven": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 7.1852e13},
 }
 
 
