@@ -227,3 +227,17 @@ def test_global_256_threads_runs_chunks_of_one(lib):
     o = dr.dr_options_default()
     o.placement, o.block, o.chunk = dr.DR_PLACE_GLOBAL, 256, 1
     assert dr.dr_batch_workspace_bytes(pk, o) > 0
+
+
+def test_rejects_bad_step_rule_options(lib):
+    """The per-pass step (dt_rule 1) is FP64 only, without the energy check
+    and without the tail hand-off; its group form takes 2..16 workgroups."""
+    pk = _packed()
+    cases = [(dict(dt_rule=2), "dt_rule"), (dict(dt_rule=1, precision=dr.DR_FP32), "FP64"),
+             (dict(dt_rule=1, energy_tol=1e-3), "energy"), (dict(dt_rule=1, tail_at=4), "hand-off"),
+             (dict(dt_rule=1, tail_group=1), "tail_group"), (dict(dt_rule=1, tail_group=17), "tail_group")]
+    for kw, msg in cases:
+        o = dr.dr_options_default()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        _expect_invalid(pk, o, msg)
