@@ -1366,10 +1366,15 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     extern __shared__ double smem[];
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id(tid);
-    // reduction records, a flag word for the group barrier, then the slice headers
-    double *red = smem;
-    int *gflag = reinterpret_cast<int *>(smem + NW * kRedStride);
-    RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + NW * kRedStride + 2);
+    // The FP64 1024-thread build stages tiles: the staged records first
+    // (kTile + the batch's largest halo, 24 bytes each), then the reduction
+    // records, a flag word for the group barrier and the slice headers.
+    constexpr bool kTileBuild = Prec::kDisp == false && sizeof(T) == 8 && BLOCK == kTile && C == 1 && !GRP;
+    const int toff = kTileBuild && A.tile_hmax > 0 ? 3 * (kTile + A.tile_hmax) : 0;
+    double *const tq = smem;
+    double *red = smem + toff;
+    int *gflag = reinterpret_cast<int *>(smem + toff + NW * kRedStride);
+    RowHdr *hdr_lds = reinterpret_cast<RowHdr *>(smem + toff + NW * kRedStride + 2);
     GroupCtx gc{nullptr, nullptr, nullptr, 1, 0, 0u};
     Slot S;
     if constexpr (GRP) {
@@ -1566,7 +1571,91 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         const int rslot = 2 * (int)(n & 1);
         gf2 = 0.0; gb2 = 0.0; ke2 = 0.0;
         const Cur cfirst = first_from(0);
-        if (cfirst.i < nrow) {
+        bool staged = false;
+        if constexpr (kTileBuild) staged = P.n_tiles > 0;
+        if constexpr (kTileBuild) if (staged) {
+            // Staged gather: tile t is this wave's row t (nodes t kTile + tid).
+            // The tile's records and its halo are copied into LDS, the
+            // incidences name their neighbour's slot there; each node's
+            // arithmetic is that of the streamed gather below.
+            const int32_t *toffs = A.tile_halo + P.tile_base;
+            const int32_t *hids = A.halo_ids + P.halo_base;
+            const uint16_t *ls = A.lslot + P.inc_base;
+            const KL *klp = A.kl + P.inc_base;
+            const LdsQ<double> tpos{reinterpret_cast<double *>(tq), 0};
+            for (int t = 0; t < P.n_tiles; ++t) {
+                const int lo = t * kTile, h0 = toffs[t], ns = kTile + toffs[t + 1] - h0;
+                for (int s = tid; s < ns; s += BLOCK) {
+                    const int j = s < kTile ? lo + s : hids[h0 + s - kTile];
+                    if (j < N) {
+                        double x, y, z;
+                        pos.load(j, x, y, z);
+                        tpos.store(s, x, y, z);
+                    }
+                }
+                __syncthreads();
+                if (t < nrow) {
+                    const RowHdr h = hdr_of(t);
+                    const int r = lo + tid;
+                    if (h.w > 0 && r < N) {
+                        // the node's state from the staged tile, its velocity and mass
+                        NodeData<T> nd;
+                        tpos.load(tid, nd.q[0], nd.q[1], nd.q[2]);
+                        nd.im = 0;
+                        nd.m = 0.0;
+                        nd.w[0] = nd.w[1] = nd.w[2] = 0;
+                        if (r < Nf) {
+                            node_mass<Prec>(A, nb, r, nd.im, nd.m);
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) nd.w[a] = node_rec<WS>(W, r)[a];
+                        }
+                        double g[3] = {0.0, 0.0, 0.0};
+                        int64_t e = (int64_t)h.off + lane;
+                        int s0 = ls[e];
+                        KL c0 = klp[e];
+                        for (int k = 0; k < h.w; ++k, e += kWave) {
+                            int s1 = 0;
+                            KL c1{0.0, 0.0};
+                            if (k + 1 < h.w) {
+                                s1 = ls[e + kWave];
+                                c1 = klp[e + kWave];
+                            }
+                            KL cc[1] = {c0};
+                            double px[1], py[1], pz[1];
+                            tpos.load(s0, px[0], py[0], pz[0]);
+                            force_pre<1>(cc, px, py, pz, af, 1, nd.q[0], nd.q[1], nd.q[2], g[0], g[1], g[2]);
+                            s0 = s1;
+                            c0 = c1;
+                        }
+                        // the node's damped acceleration, velocity updates and norm shares
+                        const double gg = sq3(g[0], g[1], g[2]);
+                        if (r < Nf) {
+                            if (A.energy_tol > 0.0)
+                                energy_pass<T>(A, nb + r, g, nd.w, nd.im, cdamp, hdt, nd.m);
+                            double vv = 0.0;
+                            T qn[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                T wa = nd.w[a];
+                                const T v = vel_step(g[a], nd.im, cdamp, hdt, wa);
+                                vv = fma((double)v, (double)v, vv);
+                                node_rec<WS>(W, r)[a] = wa;
+                                qn[a] = nd.q[a];
+                                T cn = 0;
+                                advance_q(qn[a], dt, wa, cn);
+                            }
+                            qnext.store(r, qn[0], qn[1], qn[2]);
+                            gf2 += gg;
+                            ke2 = fma(nd.m, vv, ke2);
+                        } else {
+                            gb2 += gg;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (!staged && cfirst.i < nrow) {
             // prologue: topology and neighbour states of chunk c0, topology of c1
             Cur c0 = cfirst;
             Pref<Prec, C> t0, t1;

@@ -93,6 +93,9 @@ struct dr_batch {
     double *d_X = nullptr, *d_invm = nullptr, *d_mass = nullptr;
     float *d_invm32 = nullptr, *d_mass32 = nullptr;
     int32_t *d_deg = nullptr, *d_slice_w = nullptr, *d_nbr = nullptr;
+    uint16_t *d_lslot = nullptr;
+    int32_t *d_tile_halo = nullptr, *d_halo_ids = nullptr;
+    int32_t tile_hmax = 0; // largest tile halo (0: no tiled problem)
     int64_t *d_slice_off = nullptr;
     KL *d_kl = nullptr;
     KL32 *d_kl32 = nullptr;
@@ -172,7 +175,7 @@ namespace {
 void free_all(dr_batch *b)
 {
     void *dev[] = {b->d_probs, b->d_X, b->d_invm, b->d_mass, b->d_invm32, b->d_mass32, b->d_deg,
-                   b->d_slice_w, b->d_nbr, b->d_slice_off, b->d_kl, b->d_kl32, b->d_u, b->d_qbuf,
+                   b->d_slice_w, b->d_nbr, b->d_lslot, b->d_tile_halo, b->d_halo_ids, b->d_slice_off, b->d_kl, b->d_kl32, b->d_u, b->d_qbuf,
                    b->d_wbuf, b->d_F_cur, b->d_F_last, b->d_has_state, b->d_status, b->d_sigma,
                    b->d_sigma_fib, b->d_rho, b->d_ke, b->d_iters, b->d_n_best, b->d_rho_best, b->d_F, b->d_ids, b->d_order,
                    b->d_starts, b->d_partial, b->d_scalars, b->d_gscat, b->d_enode,
@@ -255,7 +258,11 @@ struct Packed {
     std::vector<int64_t> slice_off;
     std::vector<KL> kl;
     std::vector<KL32> kl32;
+    std::vector<uint16_t> lslot;    // per incidence (tiled problems; 0 elsewhere)
+    std::vector<int32_t> tile_halo; // per tile, + 1 per tiled problem
+    std::vector<int32_t> halo_ids;
     int32_t n_max = 0;
+    int32_t tile_hmax = 0;
 };
 
 dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
@@ -392,16 +399,31 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
         const double ea_mean = M > 0 ? ea_sum / M : 0.0;
         d.s_floor = 1e-4 * ea_mean * std::sqrt(3.0 * (n_fixed > 1 ? n_fixed : 1));
 
-        // renumber: free block then prescribed block; degree descending, then Morton
+        // renumber: free block then prescribed block; degree descending, then
+        // Morton.  A problem too large for the LDS variant is cut into tiles
+        // of kTile nodes in Morton order (free block, then prescribed block),
+        // and the degree order applies inside each tile, so that a tile is a
+        // compact region whose neighbours mostly lie in the tile itself.
         std::vector<int32_t> order(N);
         std::iota(order.begin(), order.end(), 0);
         std::vector<uint32_t> key(N);
         for (int32_t i = 0; i < N; ++i) key[i] = morton3(X + 3 * i);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t i, int32_t j) {
+        auto by_degree = [&](int32_t i, int32_t j) {
             if ((fixed[i] != 0) != (fixed[j] != 0)) return fixed[i] == 0;
             if (degree[i] != degree[j]) return degree[i] > degree[j];
             return key[i] < key[j];
-        });
+        };
+        const bool tiled = N > drk::kTiledMinNodes;
+        if (tiled) {
+            std::stable_sort(order.begin(), order.end(), [&](int32_t i, int32_t j) {
+                if ((fixed[i] != 0) != (fixed[j] != 0)) return fixed[i] == 0;
+                return key[i] < key[j];
+            });
+            for (int32_t t0 = 0; t0 < N; t0 += drk::kTile)
+                std::stable_sort(order.begin() + t0, order.begin() + std::min(N, t0 + drk::kTile), by_degree);
+        } else {
+            std::stable_sort(order.begin(), order.end(), by_degree);
+        }
         HostProblem &h = pk.hp[p];
         h.N = N;
         h.N_free = n_free;
@@ -489,6 +511,62 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
         // 32-bit byte offsets
         if (off * 16 > (int64_t)INT32_MAX)
             return fail(DR_E_INVALID, "problem %d: %lld incidence entries exceed 2^27", p, (long long)off);
+        // tiles: each incidence's neighbour as a slot of its tile's staged
+        // records (the tile's own nodes first, then its halo); entries of
+        // lanes past N point at slot 0.  A problem with a halo above
+        // kHaloMax keeps the plain gather.
+        pk.lslot.resize(pk.nbr.size(), 0);
+        d.n_tiles = 0;
+        if (tiled) {
+            const int32_t nt = (N + drk::kTile - 1) / drk::kTile;
+            std::vector<int32_t> mark(N, -1), halo, toff(1, 0), ids;
+            std::vector<uint16_t> slots;
+            bool ok = true;
+            int32_t hmax = 0;
+            const int64_t e0 = (int64_t)pk.nbr.size() - off;
+            for (int32_t t = 0; t < nt && ok; ++t) {
+                const int32_t lo = t * drk::kTile, hi = std::min(N, lo + drk::kTile);
+                halo.clear();
+                for (int32_t q = lo / drk::kWave; q < (hi + drk::kWave - 1) / drk::kWave; ++q) {
+                    const int64_t so = e0 + pk.slice_off[slice_base + q];
+                    const int32_t width = pk.slice_w[slice_base + q];
+                    for (int32_t k = 0; k < width; ++k)
+                        for (int32_t lane = 0; lane < drk::kWave; ++lane) {
+                            const int64_t e = so + (int64_t)k * drk::kWave + lane;
+                            const int32_t r = q * drk::kWave + lane;
+                            int32_t slot = 0;
+                            if (r < N) {
+                                const int32_t j = pk.nbr[e];
+                                if (j >= lo && j < hi) {
+                                    slot = j - lo;
+                                } else {
+                                    if (mark[j] < 0) {
+                                        mark[j] = (int32_t)halo.size();
+                                        halo.push_back(j);
+                                    }
+                                    slot = drk::kTile + mark[j];
+                                }
+                            }
+                            pk.lslot[e] = (uint16_t)std::min(slot, 65535);
+                        }
+                }
+                for (int32_t j : halo) mark[j] = -1;
+                if ((int32_t)halo.size() > drk::kHaloMax) ok = false;
+                hmax = std::max(hmax, (int32_t)halo.size());
+                ids.insert(ids.end(), halo.begin(), halo.end());
+                toff.push_back((int32_t)ids.size());
+            }
+            if (ok) {
+                d.n_tiles = nt;
+                d.tile_base = (int64_t)pk.tile_halo.size();
+                d.halo_base = (int64_t)pk.halo_ids.size();
+                pk.tile_halo.insert(pk.tile_halo.end(), toff.begin(), toff.end());
+                pk.halo_ids.insert(pk.halo_ids.end(), ids.begin(), ids.end());
+                pk.tile_hmax = std::max(pk.tile_hmax, hmax);
+            } else {
+                std::fill(pk.lslot.begin() + e0, pk.lslot.end(), (uint16_t)0);
+            }
+        }
         d.n_inc = off;
         slice_base += d.n_slices;
         inc_base += off;
@@ -556,6 +634,9 @@ dr_status create_device(dr_batch *b, Packed &pk)
     UP(d_slice_w, slice_w)
     UP(d_slice_off, slice_off)
     UP(d_nbr, nbr)
+    UP(d_lslot, lslot)
+    UP(d_tile_halo, tile_halo)
+    UP(d_halo_ids, halo_ids)
     UP(d_kl, kl)
     UP(d_kl32, kl32)
 #undef UP
@@ -631,7 +712,7 @@ int glb_lds_bytes(int block, int G, int32_t n_max)
 
 // Launch shape for a batch whose largest problem has n_max nodes.  Returns
 // npt = -1 when DR_PLACE_LDS was asked for and the problem does not fit.
-LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
+LaunchPlan plan_for(const dr_options &opt, int32_t n_max, int32_t tile_hmax = 0)
 {
     LaunchPlan pl{};
     pl.fp32 = opt.precision == DR_FP32;
@@ -674,6 +755,10 @@ LaunchPlan plan_for(const dr_options &opt, int32_t n_max)
     }
     pl.chunk = pl.block == 256 ? 1 : (opt.chunk ? opt.chunk : (pl.block == 1024 ? 1 : 2));
     pl.lds_bytes = glb_lds_bytes(pl.block, 1, n_max);
+    // the FP64 1024-thread build stages the tiles of tiled problems (their
+    // own records and halo) in LDS, ahead of its other records
+    if (!pl.fp32 && pl.block == 1024 && pl.chunk == 1 && tile_hmax > 0)
+        pl.lds_bytes += 24 * (drk::kTile + tile_hmax);
     return pl;
 }
 
@@ -708,7 +793,7 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         o.block = r.block;
         o.chunk = r.chunk;
         o.placement = r.placement;
-        c.plan = plan_for(o, std::max(c.n_max, 1));
+        c.plan = plan_for(o, std::max(c.n_max, 1), b->tile_hmax);
         if (c.plan.npt == -2)
             return fail(DR_E_INVALID, "class up to %d nodes: global placement with 256 threads "
                         "runs gather chunks of 1 only (got %d)", r.n_hi, r.chunk);
@@ -732,7 +817,7 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         auto mc = n_max_in(lo, top);
         c.n_max = mc.first;
         c.count = mc.second;
-        c.plan = plan_for(b->opt, std::max(c.n_max, 1));
+        c.plan = plan_for(b->opt, std::max(c.n_max, 1), b->tile_hmax);
         if (c.plan.npt == -2)
             return fail(DR_E_INVALID, "global placement with 256 threads runs gather chunks of 1 only "
                         "(got %d)", b->opt.chunk);
@@ -752,7 +837,7 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
             auto mc = n_max_in(lo, fit);
             c.n_max = mc.first;
             c.count = mc.second;
-            c.plan = plan_for(b->opt, c.n_max);
+            c.plan = plan_for(b->opt, c.n_max, b->tile_hmax);
             cls.push_back(c);
             lo = fit + 1;
         }
@@ -765,7 +850,7 @@ dr_status build_classes(dr_batch *b, const std::vector<ClassRequest> &req)
         dr_options o = b->opt;
         o.placement = DR_PLACE_GLOBAL;
         if (o.block == 256) o.chunk = 1; // the only global build of that width
-        g.plan = plan_for(o, std::max(g.n_max, 1));
+        g.plan = plan_for(o, std::max(g.n_max, 1), b->tile_hmax);
         cls.push_back(g);
     }
     // classes without problems launch nothing: drop them (at least one stays)
@@ -873,6 +958,10 @@ SolveArgs make_args(dr_batch *b, int32_t n_solve, int32_t start, int64_t budget)
     a.slice_w = b->d_slice_w;
     a.slice_off = b->d_slice_off;
     a.nbr = b->d_nbr;
+    a.lslot = b->d_lslot;
+    a.tile_halo = b->d_tile_halo;
+    a.halo_ids = b->d_halo_ids;
+    a.tile_hmax = b->tile_hmax;
     a.kl = b->d_kl;
     a.kl32 = b->d_kl32;
     a.u = b->d_u;
@@ -1250,6 +1339,7 @@ dr_status create_impl(const dr_networks *nets, const dr_options *opt, void *hip_
     b->total_slices = (int64_t)pk.slice_w.size();
     b->total_inc = (int64_t)pk.nbr.size();
     b->n_max = pk.n_max;
+    b->tile_hmax = pk.tile_hmax;
     b->desc = pk.desc;
     b->running.assign(b->P, 0);
     b->last_passes.assign(b->P, 0);

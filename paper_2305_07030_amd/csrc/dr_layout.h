@@ -61,8 +61,21 @@ struct ProbDesc {
     double c;           // mass-proportional damping coefficient
     double s_floor;     // residual denominator floor
     int64_t n_inc;      // per-incidence entries of the problem (slices x 64 x width)
+    int32_t n_tiles;    // tiles of kTile nodes with halos (0: the problem has none)
+    int32_t tile_pad;
+    int64_t tile_base;  // first entry of the problem in the per-tile halo offsets
+    int64_t halo_base;  // first entry of the problem in the halo node ids
 };
-static_assert(sizeof(ProbDesc) == 72, "ProbDesc layout");
+static_assert(sizeof(ProbDesc) == 96, "ProbDesc layout");
+
+// Tiles of the global placement's staged gather: kTile consecutive nodes
+// (one per thread of a 1024-thread workgroup, one row of each wave), a
+// problem is tiled when it is too large for the LDS variant (more than
+// kTiledMinNodes nodes).  A tile's halo (the nodes outside it that its
+// incidences reach) holds at most kHaloMax nodes.
+constexpr int kTile = 1024;
+constexpr int kTiledMinNodes = 6720;
+constexpr int kHaloMax = 4096;
 
 struct KL {
     double k;  // EA / (2 L^2)
@@ -141,6 +154,10 @@ struct SolveArgs {
     uint32_t *gbar;           // [kTailMax] barrier counters of the groups
     int32_t *gabort;          // [kTailMax] abort flags of the groups
     double *gpart;            // [kTailMax * 2 * kGroupMax * 4] partial sums of the groups
+    const uint16_t *lslot;    // per incidence: the neighbour's slot in its tile's staged records
+    const int32_t *tile_halo; // per tile (+1 per problem): first entry of its halo in halo_ids
+    const int32_t *halo_ids;  // halo node ids (local to the problem)
+    int32_t tile_hmax;        // largest halo of the batch's tiles (0: no tiled problem)
     // per-pass time step (dt_rule = 1): the step's safety factor, the
     // acceleration records and the step of each running solve's next pass
     int32_t dt_rule;          // 0 = constant step, 1 = per-pass step (k_dr_dtp)

@@ -201,3 +201,39 @@ def test_all_launch_shapes_same_bits(shapes_reference, place, blk, ch):
     assert np.array_equal(g["u"], R["u"]), (place, blk, ch)
     assert np.array_equal(g["sigma"], R["sigma"]), (place, blk, ch)
     b.close()
+
+
+def test_staged_tiles_same_bits():
+    """Problems too large for the LDS variant are cut into tiles whose
+    records and halo the 1024-thread global kernel stages in LDS; every
+    node's arithmetic is the streamed gather's, so at a fixed pass count the
+    states are the same bits as the streamed 256- and 512-thread builds, in
+    one launch and across budgeted launches."""
+    rng = np.random.default_rng(66)
+    nets = [I.draw_network(rng, n) for n in (3000, 6721, 7000, 15000, 33000)]
+    batch = I.Batch(nets, np.stack([I.sym_perturbed_F(rng, 0.02) for _ in nets]))
+    kw = dict(tol=1e-300, max_iter=400, damping=1e-3, placement=dr.DR_PLACE_GLOBAL)
+    out = {}
+    for blk in (1024, 512, 256):
+        b = dr.DRBatch(batch, block=blk, chunk=1, **kw)
+        b.solve()
+        out[blk] = b.results(want_u=True)
+        b.close()
+    for blk in (512, 256):
+        assert np.array_equal(out[1024]["iters"], out[blk]["iters"])
+        assert np.array_equal(out[1024]["u"], out[blk]["u"])
+        assert np.array_equal(out[1024]["sigma"], out[blk]["sigma"])
+    # the default split: the 3000-node network in LDS, the rest staged
+    b = dr.DRBatch(batch, tol=1e-300, max_iter=400, damping=1e-3)
+    ids = np.arange(len(batch), dtype=np.int32)
+    b.advance(ids, np.full(len(ids), dr.DR_START_AFFINE, np.int32), 150, F=batch.F)
+    for _ in range(5):
+        run = ids[b.query(ids)["result"] == dr.DR_RUNNING]
+        if len(run) == 0:
+            break
+        b.advance(run, np.full(len(run), dr.DR_RESUME, np.int32), 150)
+    q = b.query(ids)
+    b.close()
+    say("staged tiles: passes", q["iters"].tolist())
+    assert np.array_equal(q["iters"], out[1024]["iters"])
+    assert np.array_equal(q["sigma"], out[1024]["sigma"])
