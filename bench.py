@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {
     "uniform32": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 1.4187e13},
     # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels and the stress of one 20 000-pass
     # launch (default plans), per launch of the two the run makes
-    "uneven": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 7.1852e13},
+    "uneven": {"kernels": "e255cf9c0b2a17b7", "bytes_per_launch": 4.4023e13},
 }
 
 
