@@ -1369,7 +1369,7 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
     // The FP64 1024-thread build stages tiles: the staged records first
     // (kTile + the batch's largest halo, 24 bytes each), then the reduction
     // records, a flag word for the group barrier and the slice headers.
-    constexpr bool kTileBuild = Prec::kDisp == false && sizeof(T) == 8 && BLOCK == kTile && C == 1 && !GRP;
+    constexpr bool kTileBuild = Prec::kDisp == false && sizeof(T) == 8 && BLOCK == kTile && C == 1;
     const int toff = kTileBuild && A.tile_hmax > 0 ? 3 * (kTile + A.tile_hmax) : 0;
     double *const tq = smem;
     double *red = smem + toff;
@@ -1574,8 +1574,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
         bool staged = false;
         if constexpr (kTileBuild) staged = P.n_tiles > 0;
         if constexpr (kTileBuild) if (staged) {
-            // Staged gather: tile t is this wave's row t (nodes t kTile + tid).
-            // The tile's records and its halo are copied into LDS, the
+            // Staged gather: row i of this wave is tile i G + member (nodes
+            // t kTile + tid).  The tile's records and its halo are copied into LDS, the
             // incidences name their neighbour's slot there; each node's
             // arithmetic is that of the streamed gather below.
             const int32_t *toffs = A.tile_halo + P.tile_base;
@@ -1583,8 +1583,13 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
             const uint16_t *ls = A.lslot + P.inc_base;
             const KL *klp = A.kl + P.inc_base;
             const LdsQ<double> tpos{reinterpret_cast<double *>(tq), 0};
-            for (int t = 0; t < P.n_tiles; ++t) {
-                const int lo = t * kTile, h0 = toffs[t], ns = kTile + toffs[t + 1] - h0;
+            // row i of the (virtual) workgroup is tile i G + member
+            const int nit = (P.n_tiles + gc.G - 1) / gc.G;
+            for (int i = 0; i < nit; ++i) {
+                const int t = i * gc.G + gc.member;
+                const int lo = t * kTile;
+                const int h0 = t < P.n_tiles ? toffs[t] : 0;
+                const int ns = t < P.n_tiles ? kTile + toffs[t + 1] - h0 : 0;
                 for (int s = tid; s < ns; s += BLOCK) {
                     const int j = s < kTile ? lo + s : hids[h0 + s - kTile];
                     if (j < N) {
@@ -1594,8 +1599,8 @@ __global__ void __launch_bounds__(BLOCK) k_dr_glb(SolveArgs A)
                     }
                 }
                 __syncthreads();
-                if (t < nrow) {
-                    const RowHdr h = hdr_of(t);
+                if (i < nrow) {
+                    const RowHdr h = hdr_of(i);
                     const int r = lo + tid;
                     if (h.w > 0 && r < N) {
                         // the node's state from the staged tile, its velocity and mass

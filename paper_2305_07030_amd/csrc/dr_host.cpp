@@ -902,6 +902,7 @@ dr_status plan_tail(dr_batch *b)
     for (int pass = 0; pass < 2; ++pass) {
         const int g_try = G > 0 ? G : 2;
         pl.lds_bytes = glb_lds_bytes(pl.block, g_try, b->n_max);
+        if (!pl.fp32 && b->tile_hmax > 0) pl.lds_bytes += 24 * (drk::kTile + b->tile_hmax);
         int cap = 0;
         const int rc = drk::group_grid_capacity(pl.fp32, pl.block, pl.lds_bytes, &cap);
         if (rc != 0) return fail(DR_E_DEVICE, "group kernel occupancy: %s", drk::kernel_error_string(rc));
@@ -920,6 +921,8 @@ dr_status plan_tail(dr_batch *b)
         break;
     }
     pl.lds_bytes = glb_lds_bytes(pl.block, G, b->n_max);
+    // the FP64 group kernel stages tiles as the 1024-thread global build does
+    if (!pl.fp32 && b->tile_hmax > 0) pl.lds_bytes += 24 * (drk::kTile + b->tile_hmax);
     b->tail_plan = pl;
     b->tail_group = G;
     return DR_OK;
