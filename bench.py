@@ -47,13 +47,13 @@ PEAK_HBM = 8.0e12
 # and the commands).  Valid only for the kernel source it was measured on:
 # any change to the kernels makes the figure null until it is measured again.
 MEASURED_TRAFFIC = {
-    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7.15524e9 KiB x 1.9998 + WRITE 18354.8 KiB x 1.0
-    "uniform": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 1.4652e13},
-    # profiles/k_dr_reg_uniform256_fp32.md: FETCH 6.92797e9 KiB x 1.9998 + WRITE 18356.4 KiB x 1.0
-    "uniform32": {"kernels": "d93301d7781cdfb2", "bytes_per_launch": 1.4187e13},
+    # profiles/k_dr_reg_uniform256_fp64.md: FETCH 7.15131e9 KiB x 1.9998 + WRITE 18354.5 KiB x 1.0
+    "uniform": {"kernels": "b0d5014e1253bb79", "bytes_per_launch": 1.4644e13},
+    # profiles/k_dr_reg_uniform256_fp32.md: FETCH 6.94796e9 KiB x 1.9998 + WRITE 18357.3 KiB x 1.0
+    "uniform32": {"kernels": "b0d5014e1253bb79", "bytes_per_launch": 1.4228e13},
     # profiles/k_dr_glb_uneven1024_fp64.md: both DR kernels and the stress of one 20 000-pass
     # launch (default plans), per launch of the two the run makes
-    "uneven": {"kernels": "e255cf9c0b2a17b7", "bytes_per_launch": 4.4023e13},
+    "uneven": {"kernels": "b0d5014e1253bb79", "bytes_per_launch": 4.4016e13},
 }
 
 
