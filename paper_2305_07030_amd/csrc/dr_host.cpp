@@ -572,6 +572,8 @@ dr_status pack(const dr_networks *nets, const dr_options *opt, Packed &pk)
         inc_base += off;
         node_base += N;
     }
+    // without a tiled problem the kernels never read the slots
+    if (pk.tile_hmax == 0 && pk.tile_halo.empty()) pk.lslot.clear();
     return DR_OK;
 }
 

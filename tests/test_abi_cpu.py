@@ -241,3 +241,23 @@ def test_rejects_bad_step_rule_options(lib):
         for k, v in kw.items():
             setattr(o, k, v)
         _expect_invalid(pk, o, msg)
+
+
+def test_tiles_only_above_the_lds_limit(lib):
+    """A problem of more than 6720 nodes (too large for the LDS variant) is
+    packed with tiles: a 2-byte neighbour slot per incidence entry (at least
+    two per fiber) plus its tiles' halo lists, which the workspace accounts
+    for; a batch whose problems all fit in LDS carries none."""
+    rng = np.random.default_rng(5)
+
+    def bytes_for(n):
+        net = I.draw_network(rng, n)
+        pk = I.Batch([net], np.eye(3)[None]).packed()
+        return dr.dr_batch_workspace_bytes(pk, dr.dr_options_default()), net.n_fibers
+    small, m_small = bytes_for(6720)
+    big, m_big = bytes_for(6721)
+    # the two networks differ by a few fibers (per fiber: two 20-byte
+    # incidence entries, two degrees' worth of rounding); 256-byte rounding
+    # of every array
+    slack = 64 * abs(m_big - m_small) + 64 * 256
+    assert big - small >= 2 * 2 * m_big - slack
