@@ -185,9 +185,9 @@ typedef struct {
  *               8 x tail_group x ceil(n / 8) workgroups must fit on the
  *               device at once (the runtime refuses the launch otherwise:
  *               DR_E_DEVICE); size-class plans are DR_E_INVALID.
- *   dt_rule     0 = one constant step per solve (reading R3 of Fig. 1's
- *               "compute next time step"); 1 = a step per pass from the
- *               current state (reading R16): dt_n = min(dt_{n-1},
+ *   dt_rule     0 = one constant step per solve (Fig. 1's "compute next
+ *               time step" read as fixed for the solve); 1 = a step per
+ *               pass from the current state: dt_n = min(dt_{n-1},
  *               dt_safety * 2 / w), w^2 = max over free nodes i of
  *               (2 / m_i) sum_{f at i} EA_f l_f / L_f^2 (axial tangent
  *               stiffness at the current length), from dt_0 = the constant
