@@ -133,7 +133,13 @@ typedef struct {
  *   block       threads per workgroup: 0 = automatic, else 256, 512 or 1024
  *   placement   a dr_placement value; DR_PLACE_LDS is rejected at creation
  *               when the largest problem does not fit (3 * 8 B per node of
- *               LDS, at most 8 nodes per thread)
+ *               LDS, at most 8 nodes per thread).  A problem of more than
+ *               6720 nodes is packed in spatial tiles of 1024 nodes, and
+ *               the FP64 global placement with 1024 threads and chunks of 1
+ *               (the automatic choice for such problems, also in groups)
+ *               stages each tile's states and those of its halo in LDS
+ *               before gathering; the results are the same bits as the
+ *               other global builds'.
  *   chunk       incidences per step of the force gather, whose loads are
  *               issued one step ahead: 0 = automatic, else 1, 2 or 4 (a
  *               tuning knob; results do not depend on it).  Global placement
