@@ -154,8 +154,9 @@ def test_budgeted_launches_equal_one_launch():
 def test_diverging_uneven_networks_converge():
     """The four networks of the 1024-network workload whose constant-step
     solves diverge (a fiber crushed and then stretched beyond the step's
-    headroom): with the per-pass step all converge, to the oracle's stress
-    (bar: 1e-8, or 100x the oracle's own spread over perturbed starts)."""
+    headroom): with the per-pass step (in groups of 16 workgroups, as the
+    benchmark re-solves them) all converge, to the oracle's stress (bar:
+    1e-8, or 100x the oracle's own spread over perturbed starts)."""
     path = os.path.join(GOLDEN, "uneven1024_steprule.json")
     if not os.path.exists(path):
         pytest.skip("the oracle's results for these networks (make_oracle_golden.py uneven_steprule) "
@@ -167,7 +168,7 @@ def test_diverging_uneven_networks_converge():
     kw = dict(tol=1e-8, damping=G["damping"])
     r0 = solve(sub, tol=1e-8, max_iter=5000, damping=G["damping"])
     assert (r0["result"] == dr.DR_NONFINITE).all()
-    g = solve(sub, dt_rule=1, **kw)
+    g = solve(sub, dt_rule=1, tail_group=16, **kw)
     for k, e in enumerate(G["networks"]):
         o = e["tol_1e-08"]["plain"]
         s0 = np.array(o["sigma"])
